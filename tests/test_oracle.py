@@ -171,7 +171,7 @@ def test_loss_gradient_matches_full_gradient():
 
 
 def test_loss_regularises_only_observed_rows():
-    cfg, p, params = _problem("tiny3", matrices=(), nnz=12)
+    cfg, p, params = _problem("tiny3", matrices=(), nnz=12, dims=(10, 8, 9))
     cnt, cntV = oracle.counts(params, p)
     f0 = oracle.loss(params, p)[0]
     # rows never observed in training carry no regularisation: moving them
