@@ -31,6 +31,7 @@ from .api import (  # noqa: F401
     matrix_predict,
     tensor_item_grad,
     tensor_item_grad_opt,
+    tensor_item_w,
     matrix_item_grad,
     sgd_epoch,
     minibatch_epoch,

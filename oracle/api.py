@@ -84,7 +84,8 @@ def _L():
         lib.or_sgd_epoch.argtypes = [M, T, C.c_int32, Y, Cn, H, _i64p, C.c_int64, C.c_double]
         lib.or_sgd_epoch.restype = C.c_int64
         lib.or_minibatch_epoch.argtypes = [M, T, C.c_int32, Y, Cn, H, _i64p, C.c_int64,
-                                           C.c_int64, C.c_double, C.c_int64, C.c_int64]
+                                           C.c_int64, C.c_double, C.c_int64, C.c_int64, C.c_int32]
+        lib.or_tensor_item_w.argtypes = [M, _i32p, _dp]
         lib.or_minibatch_epoch.restype = C.c_int64
         lib.or_loss.argtypes = [M, T, C.c_int32, Y, Cn, H, _dp]
         lib.or_rmse.argtypes = [M, T]
@@ -235,6 +236,16 @@ def tensor_item_grad_opt(params: Params, rows, x, reg_row, reg_core):
     return e, np.split(gU, np.cumsum(Js)[:-1]), gG.reshape(params.G.shape), S.reshape(params.G.shape)
 
 
+def tensor_item_w(params: Params, rows):
+    """Leave-one-out contractions G x_{-n} {u} of one entry (Eq 3 / Eq 8)."""
+    md = params._model()
+    rows = _i32(rows)
+    Js = [u.shape[1] for u in params.U]
+    w = np.empty(sum(Js))
+    _L().or_tensor_item_w(C.byref(md), _ptr(rows, _i32p), _ptr(w, _dp))
+    return np.split(w, np.cumsum(Js)[:-1])
+
+
 def matrix_item_grad(u, v, y, lambda_m, reg_v):
     u, v = _f64(u), _f64(v)
     gu, gv = np.empty_like(u), np.empty_like(v)
@@ -272,14 +283,15 @@ def sgd_epoch(params: Params, problem, order, eta: float, lambda_reg=None, lambd
 
 
 def minibatch_epoch(params: Params, problem, order, batch: int, eta: float, first_batch: int = 0,
-                    n_batches: int = -1, lambda_reg=None, lambda_m=None) -> int:
-    """Deterministic mini-batch pass (batch-start gradients summed, then applied). In place."""
+                    n_batches: int = -1, lambda_reg=None, lambda_m=None, damping: bool = False) -> int:
+    """Deterministic mini-batch pass (batch-start gradients summed, then applied,
+    optionally with the curvature damping of each block's step). In place."""
     lr, lm = _hyper(problem, lambda_reg, lambda_m)
     r = _Run(params, problem, lr, lm)
     order = np.ascontiguousarray(order, dtype=np.int64)
     return int(_L().or_minibatch_epoch(C.byref(r.md), C.byref(r.d.X), r.d.M, r.d.Y, C.byref(r.ch.c),
                                        C.byref(r.h), _ptr(order, _i64p), order.shape[0], int(batch),
-                                       float(eta), int(first_batch), int(n_batches)))
+                                       float(eta), int(first_batch), int(n_batches), int(bool(damping))))
 
 
 def loss(params: Params, problem, lambda_reg=None, lambda_m=None):

@@ -193,6 +193,26 @@ double or_tensor_item_grad(const or_model *md, const int32_t *rows, double x,
     return e;
 }
 
+/* The leave-one-out contractions w_n = G x_{-n} {u} of one entry (Eq 3 /
+ * Eq 8), straight from the definition; w receives J_1 + ... + J_N values. */
+void or_tensor_item_w(const or_model *md, const int32_t *rows, double *w)
+{
+    int64_t K = core_size(md);
+    int32_t jj[OR_MAXN];
+    int64_t off = 0;
+    for (int n = 0; n < md->N; ++n) {
+        for (int k = 0; k < md->J[n]; ++k) w[off + k] = 0.0;
+        for (int64_t j = 0; j < K; ++j) {
+            decode(md, j, jj);
+            double p = md->G[j];
+            for (int m = 0; m < md->N; ++m)
+                if (m != n) p *= urow(md, m, rows[m])[jj[m]];
+            w[off + jj[n]] += p;
+        }
+        off += md->J[n];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* The same gradients in the paper's reuse form (Definition 4, Lemma 2,
  * Definition 5, Lemma 3, Algorithm 3): S = G * (u^(1) o ... o u^(N)),
@@ -349,12 +369,27 @@ int64_t or_sgd_epoch(or_model *md, const or_tensor *X, int32_t M, const or_matri
  * item's gradients are taken at the batch-start values, summed per
  * parameter, and each parameter moves by -eta times its sum.  Runs the
  * batches [first_batch, first_batch + n_batches) (n_batches < 0: to the
- * end).  Returns the number of batches run.                             */
+ * end).  Returns the number of batches run.
+ *
+ * damping != 0 selects the library's damped reading: each parameter block
+ * (a factor row, a coupled-factor row, the core) also sums the curvature
+ * L of its contributions -- |w_n|^2 + lambda_reg / cnt_n for a tensor
+ * row, prod_n |u^(n)|^2 + lambda_reg / |Omega_X| for the core,
+ * lambda_m |v|^2 for the coupled-mode row of a matrix entry and
+ * lambda_m |u|^2 + lambda_m lambda_reg / cntV for its V row -- and moves
+ * by -eta / max(1, (N + 1) eta L) times its gradient sum.               */
+
+static double damped(double eta, double kappa, double L, int damping)
+{
+    if (!damping) return eta;
+    double d = kappa * eta * L;
+    return eta / (d > 1.0 ? d : 1.0);
+}
 
 int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or_matrix *Y,
                            const or_counts *c, const or_hyper *h, const int64_t *order,
                            int64_t n_order, int64_t batch, double eta,
-                           int64_t first_batch, int64_t n_batches)
+                           int64_t first_batch, int64_t n_batches, int32_t damping)
 {
     or_ctx cx;
     ctx_init(&cx, md, X, M, Y, c, h);
@@ -370,6 +405,12 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
     double *gG = (double *)malloc(sizeof(double) * (size_t)K);
     double *gu = (double *)malloc(sizeof(double) * (size_t)R);
     double *gv = (double *)malloc(sizeof(double) * (size_t)R);
+    double *w = (double *)malloc(sizeof(double) * (size_t)R);
+    double *LU[OR_MAXN], *LV[OR_MAXM];
+    for (int n = 0; n < N; ++n) LU[n] = (double *)calloc((size_t)md->dims[n], sizeof(double));
+    for (int m = 0; m < M; ++m) LV[m] = (double *)calloc((size_t)md->cols[m], sizeof(double));
+    double LG = 0.0;
+    double kappa = (double)(N + 1);
     int32_t rows[OR_MAXN];
     double reg_row[OR_MAXN];
     double reg_core = h->lambda_reg / (double)c->nX;
@@ -394,6 +435,20 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
                     off += md->J[n];
                 }
                 for (int64_t j = 0; j < K; ++j) aG[j] += gG[j];
+                if (damping) {
+                    or_tensor_item_w(md, rows, w);
+                    double pu = 1.0;
+                    off = 0;
+                    for (int n = 0; n < N; ++n) {
+                        const double *u = urow(md, n, rows[n]);
+                        double ww = 0.0, uu = 0.0;
+                        for (int k = 0; k < md->J[n]; ++k) { ww += w[off + k] * w[off + k]; uu += u[k] * u[k]; }
+                        LU[n][rows[n]] += ww + reg_row[n];
+                        pu *= uu;
+                        off += md->J[n];
+                    }
+                    LG += pu + reg_core;
+                }
             } else {
                 int64_t e;
                 int m = item_matrix(&cx, id, &e);
@@ -406,6 +461,12 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
                 double *au = aU[cm] + (int64_t)Y[m].row[e] * J;
                 double *av = aV[m] + (int64_t)Y[m].col[e] * J;
                 for (int k = 0; k < J; ++k) { au[k] += gu[k]; av[k] += gv[k]; }
+                if (damping) {
+                    double uu = 0.0, vv = 0.0;
+                    for (int k = 0; k < J; ++k) { uu += u[k] * u[k]; vv += v[k] * v[k]; }
+                    LU[cm][Y[m].row[e]] += h->lambda_m * vv;
+                    LV[m][Y[m].col[e]] += h->lambda_m * uu + h->lambda_m * reg_v;
+                }
             }
         }
         /* 2: apply and clear the touched accumulators */
@@ -416,7 +477,9 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
                     int64_t i = X->idx[n * X->nnz + id];
                     double *u = md->U[n] + i * md->J[n];
                     double *a = aU[n] + i * md->J[n];
-                    for (int k = 0; k < md->J[n]; ++k) { u[k] -= eta * a[k]; a[k] = 0.0; }
+                    double st = damped(eta, kappa, LU[n][i], damping);
+                    for (int k = 0; k < md->J[n]; ++k) { u[k] -= st * a[k]; a[k] = 0.0; }
+                    LU[n][i] = 0.0;
                 }
             } else {
                 int64_t e;
@@ -427,18 +490,24 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
                 double *au = aU[cm] + (int64_t)Y[m].row[e] * J;
                 double *v = md->V[m] + (int64_t)Y[m].col[e] * J;
                 double *av = aV[m] + (int64_t)Y[m].col[e] * J;
+                double su = damped(eta, kappa, LU[cm][Y[m].row[e]], damping);
+                double sv = damped(eta, kappa, LV[m][Y[m].col[e]], damping);
                 for (int k = 0; k < J; ++k) {
-                    u[k] -= eta * au[k]; au[k] = 0.0;
-                    v[k] -= eta * av[k]; av[k] = 0.0;
+                    u[k] -= su * au[k]; au[k] = 0.0;
+                    v[k] -= sv * av[k]; av[k] = 0.0;
                 }
+                LU[cm][Y[m].row[e]] = 0.0;
+                LV[m][Y[m].col[e]] = 0.0;
             }
         }
-        for (int64_t j = 0; j < K; ++j) { md->G[j] -= eta * aG[j]; aG[j] = 0.0; }
+        double sg = damped(eta, kappa, LG, damping);
+        for (int64_t j = 0; j < K; ++j) { md->G[j] -= sg * aG[j]; aG[j] = 0.0; }
+        LG = 0.0;
         ++done;
     }
-    for (int n = 0; n < N; ++n) free(aU[n]);
-    for (int m = 0; m < M; ++m) free(aV[m]);
-    free(aG); free(gU); free(gG); free(gu); free(gv);
+    for (int n = 0; n < N; ++n) { free(aU[n]); free(LU[n]); }
+    for (int m = 0; m < M; ++m) { free(aV[m]); free(LV[m]); }
+    free(aG); free(gU); free(gG); free(gu); free(gv); free(w);
     return done;
 }
 

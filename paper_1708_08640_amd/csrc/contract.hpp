@@ -1,0 +1,127 @@
+// Per-entry Tucker contractions on one lane.
+//
+// For one observed entry with factor rows u^(1..N) (held in registers, zero
+// padded to JP) and the core G (JP^N, row-major, zero padded), compute in a
+// single pass over G:
+//   w_n[k] = [G x_{-n} {u}]_k   (the leave-one-out contraction of Eq 8)
+//   x~     = G x {u}            (Eq 4)
+// Every core element is read once and feeds two fused multiply-adds: one
+// into the contraction with the innermost factor (a running partial sum
+// that is reused for all outer modes) and one into w_N.  This is the
+// paper's reuse of intermediate products (Definition 4, Lemma 2,
+// Algorithm 3) in a division-free form: partial contractions are kept and
+// re-used instead of dividing the full product by a factor entry.
+// Cost: 2 * JP^N FMAs plus O(N * JP^(N-1)).
+#pragma once
+#include "common.hpp"
+
+namespace s3 {
+
+template <int JP, typename T, typename GP>
+S3_DEV void contract3(GP G, const T (&a)[JP], const T (&b)[JP], const T (&c)[JP],
+                      T (&w1)[JP], T (&w2)[JP], T (&w3)[JP], T &xhat) {
+#pragma unroll
+    for (int k = 0; k < JP; ++k) { w2[k] = T(0); w3[k] = T(0); }
+#pragma unroll
+    for (int j1 = 0; j1 < JP; ++j1) {
+        T s1 = T(0);
+#pragma unroll
+        for (int j2 = 0; j2 < JP; ++j2) {
+            const T ab = a[j1] * b[j2];
+            T t = T(0);
+#pragma unroll
+            for (int j3 = 0; j3 < JP; ++j3) {
+                const T g = G[(j1 * JP + j2) * JP + j3];
+                t = fmaT(g, c[j3], t);          // (G x_3 c)[j1][j2]
+                w3[j3] = fmaT(ab, g, w3[j3]);   // (G x_1 a x_2 b)[j3]
+            }
+            w2[j2] = fmaT(a[j1], t, w2[j2]);
+            s1 = fmaT(b[j2], t, s1);
+        }
+        w1[j1] = s1;
+    }
+    T x = T(0);
+#pragma unroll
+    for (int k = 0; k < JP; ++k) x = fmaT(w3[k], c[k], x);
+    xhat = x;
+}
+
+template <int JP, typename T, typename GP>
+S3_DEV void contract4(GP G, const T (&a)[JP], const T (&b)[JP], const T (&c)[JP],
+                      const T (&d)[JP], T (&w1)[JP], T (&w2)[JP], T (&w3)[JP], T (&w4)[JP],
+                      T &xhat) {
+#pragma unroll
+    for (int k = 0; k < JP; ++k) { w2[k] = T(0); w3[k] = T(0); w4[k] = T(0); }
+#pragma unroll
+    for (int j1 = 0; j1 < JP; ++j1) {
+        T s1 = T(0);
+#pragma unroll
+        for (int j2 = 0; j2 < JP; ++j2) {
+            const T ab = a[j1] * b[j2];
+            T s2 = T(0);
+#pragma unroll
+            for (int j3 = 0; j3 < JP; ++j3) {
+                const T abc = ab * c[j3];
+                T t = T(0);
+#pragma unroll
+                for (int j4 = 0; j4 < JP; ++j4) {
+                    const T g = G[((j1 * JP + j2) * JP + j3) * JP + j4];
+                    t = fmaT(g, d[j4], t);
+                    w4[j4] = fmaT(abc, g, w4[j4]);
+                }
+                w3[j3] = fmaT(ab, t, w3[j3]);
+                s2 = fmaT(c[j3], t, s2);
+            }
+            w2[j2] = fmaT(a[j1], s2, w2[j2]);
+            s1 = fmaT(b[j2], s2, s1);
+        }
+        w1[j1] = s1;
+    }
+    T x = T(0);
+#pragma unroll
+    for (int k = 0; k < JP; ++k) x = fmaT(w4[k], d[k], x);
+    xhat = x;
+}
+
+// N-generic front end: rows u[n][k], outputs w[n][k]
+template <int N, int JP, typename T, typename GP>
+S3_DEV void contract(GP G, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {
+    if constexpr (N == 3) {
+        contract3<JP, T>(G, u[0], u[1], u[2], w[0], w[1], w[2], xhat);
+    } else {
+        contract4<JP, T>(G, u[0], u[1], u[2], u[3], w[0], w[1], w[2], w[3], xhat);
+    }
+}
+
+// prediction only (Eq 4): same pass without the w_n outputs for outer modes
+template <int N, int JP, typename T, typename GP>
+S3_DEV T predict(GP G, const T (&u)[N][JP]) {
+    T acc = T(0);
+    if constexpr (N == 3) {
+#pragma unroll
+        for (int j1 = 0; j1 < JP; ++j1)
+#pragma unroll
+            for (int j2 = 0; j2 < JP; ++j2) {
+                T t = T(0);
+#pragma unroll
+                for (int j3 = 0; j3 < JP; ++j3) t = fmaT(G[(j1 * JP + j2) * JP + j3], u[2][j3], t);
+                acc = fmaT(u[0][j1] * u[1][j2], t, acc);
+            }
+    } else {
+#pragma unroll
+        for (int j1 = 0; j1 < JP; ++j1)
+#pragma unroll
+            for (int j2 = 0; j2 < JP; ++j2)
+#pragma unroll
+                for (int j3 = 0; j3 < JP; ++j3) {
+                    T t = T(0);
+#pragma unroll
+                    for (int j4 = 0; j4 < JP; ++j4)
+                        t = fmaT(G[((j1 * JP + j2) * JP + j3) * JP + j4], u[3][j4], t);
+                    acc = fmaT(u[0][j1] * u[1][j2] * u[2][j3], t, acc);
+                }
+    }
+    return acc;
+}
+
+}  // namespace s3

@@ -1,0 +1,571 @@
+// gfx950 kernels for sparse coupled Tucker SGD.
+//
+// Hot path of one deterministic mini-batch step (item order cut into
+// batches; all gradients at the batch-start values):
+//   k_det_tensor      one lane per tensor entry: gather the N factor rows,
+//                     single pass over the core (contract.hpp) -> x~, e,
+//                     w_n; write the row gradients of Eq (8) and the scalar
+//                     -e to a per-batch scratch row
+//   k_det_matrix      one lane per coupled-matrix entry: u.v, e, both row
+//                     gradients of Eq (8)
+//   k_core_partial    core gradient sum_t (-e_t) u^(1)_t o ... o u^(N)_t
+//                     over a fixed chunk of entries: each thread owns one
+//                     index of modes 2..N and all J_1 accumulators, entries
+//                     are staged through LDS
+//   k_rows_apply      one wavefront per touched row: sums that row's
+//                     contributions in a fixed order (lanes stride the list,
+//                     then a fixed butterfly), applies -eta * sum
+//   k_core_apply      sums the chunk partials in order, adds the
+//                     regulariser, applies
+// All reductions have a fixed order, so a det-mode run is bitwise
+// reproducible.
+#pragma once
+#include "common.hpp"
+#include "contract.hpp"
+
+namespace s3 {
+
+constexpr int kMaxN = 4;
+constexpr int kMaxM = 4;
+constexpr int kChunk = 256;  // entries per core-gradient chunk
+
+template <typename T> struct TensorArgs {
+    const int32_t *idx;  // [N][nnz]
+    int64_t nnz;
+    const T *val;
+    T *U[kMaxN];
+    int J[kMaxN];
+    const int32_t *cnt[kMaxN];
+    T lambda_reg;
+};
+
+// ----------------------------------------------------------------------- prep
+
+__global__ void k_check_range(const int32_t *__restrict__ idx, int64_t n, int64_t limit,
+                              int32_t *__restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (; i < n; i += stride) {
+        const int32_t v = idx[i];
+        bad |= (v < 0) | ((int64_t)v >= limit);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void k_hist(const int32_t *__restrict__ idx, int64_t n, int32_t *__restrict__ cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) atomicAdd(&cnt[idx[i]], 1);
+}
+
+// key = batch * (M + 1) + type (0 tensor, m + 1 matrix m); value = item id
+__global__ void k_order_keys(const int32_t *__restrict__ order, int64_t n, int64_t batch,
+                             int64_t nX, int32_t M, const int64_t *__restrict__ mat_end,
+                             uint32_t *__restrict__ key, int32_t *__restrict__ val) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; t < n; t += stride) {
+        const int64_t id = order[t];
+        int type = 0;
+        if (id >= nX) {
+            type = 1;
+            for (int m = 0; m < M; ++m)
+                if (id >= mat_end[m]) type = m + 2;
+        }
+        key[t] = (uint32_t)((t / batch) * (M + 1) + type);
+        val[t] = (int32_t)id;
+    }
+}
+
+// off[k] = first position whose key >= k, for k in [0, nkeys]; keys sorted
+template <typename K>
+__global__ void k_bounds(const K *__restrict__ key, int64_t n, int64_t nkeys,
+                         int64_t *__restrict__ off) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; p <= n; p += stride) {
+        const int64_t lo = (p == 0) ? -1 : (int64_t)key[p - 1];
+        const int64_t hi = (p == n) ? nkeys : (int64_t)key[p];
+        for (int64_t k = lo + 1; k <= hi && k <= nkeys; ++k) off[k] = p;
+    }
+}
+
+// Contributions of every sorted item position to one parameter group.
+// Group g < N: rows of U^(g) (tensor entries, and entries of matrices
+// coupled to mode g).  Group N + m: rows of V_m.  key = (batch << 32) | row,
+// val = gradient offset | (curvature offset << 32) into the batch scratch.
+// Positions that do not touch the group get key ~0 and sort last.
+struct GroupArgs {
+    const int32_t *sorted_ids;   // item ids grouped by (batch, type)
+    const uint32_t *sorted_keys; // their (batch, type) keys
+    const int64_t *type_off;     // first position of each (batch, type) key
+    int64_t n;
+    int32_t M;
+    int32_t N;
+    int32_t group;
+    int64_t nX;
+    const int32_t *x_idx;
+    int64_t x_nnz;
+    const int32_t *y_row[kMaxM];
+    const int32_t *y_col[kMaxM];
+    int64_t mat_begin[kMaxM];
+    int32_t mat_mode[kMaxM];
+    int64_t t_stride;      // floats per tensor scratch row
+    int64_t t_goff;        // offset of this group's gradient in a tensor row
+    int64_t t_coff;        // offset of this group's curvature in a tensor row
+    int64_t m_base[kMaxM]; // start of each matrix's scratch region
+    int64_t m_stride[kMaxM];
+    int32_t m_J[kMaxM];
+};
+
+__global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_out,
+                                uint64_t *__restrict__ val_out) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; p < a.n; p += stride) {
+        const uint32_t k = a.sorted_keys[p];
+        const int64_t b = k / (a.M + 1);
+        const int type = (int)(k % (a.M + 1));
+        const int64_t slot = p - a.type_off[k];
+        const int64_t id = a.sorted_ids[p];
+        uint64_t kk = ~0ull, vv = 0;
+        if (type == 0) {
+            if (a.group < a.N) {
+                const int64_t row = a.x_idx[(int64_t)a.group * a.x_nnz + id];
+                const int64_t go = slot * a.t_stride + a.t_goff;
+                const int64_t co = slot * a.t_stride + a.t_coff;
+                kk = ((uint64_t)b << 32) | (uint64_t)row;
+                vv = (uint64_t)go | ((uint64_t)co << 32);
+            }
+        } else {
+            const int m = type - 1;
+            const int64_t e = id - a.mat_begin[m];
+            const int64_t base = a.m_base[m] + slot * a.m_stride[m];
+            const int J = a.m_J[m];
+            if (a.group == a.mat_mode[m]) {
+                kk = ((uint64_t)b << 32) | (uint64_t)a.y_row[m][e];
+                vv = (uint64_t)base | ((uint64_t)(base + 2 * J) << 32);
+            } else if (a.group == a.N + m) {
+                kk = ((uint64_t)b << 32) | (uint64_t)a.y_col[m][e];
+                vv = (uint64_t)(base + J) | ((uint64_t)(base + 2 * J + 1) << 32);
+            }
+        }
+        key_out[p] = kk;
+        val_out[p] = vv;
+    }
+}
+
+__global__ void k_seg_flags(const uint64_t *__restrict__ key, int64_t n, int32_t *__restrict__ flag) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; p < n; p += stride) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
+}
+
+// seg_id = inclusive scan of flags - 1
+__global__ void k_seg_write(const uint64_t *__restrict__ key, const int32_t *__restrict__ flag,
+                            const int32_t *__restrict__ seg_id, int64_t n,
+                            int64_t *__restrict__ seg_start, int32_t *__restrict__ seg_row,
+                            uint32_t *__restrict__ seg_batch) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; p < n; p += stride) {
+        if (flag[p]) {
+            const int64_t s = seg_id[p] - 1;
+            seg_start[s] = p;
+            seg_row[s] = (int32_t)(key[p] & 0xffffffffull);
+            seg_batch[s] = (uint32_t)(key[p] >> 32);
+        }
+        if (p == n - 1) seg_start[seg_id[p]] = n;
+    }
+}
+
+// --------------------------------------------------------------- core padding
+
+// copy the core J_1 x .. x J_N into a zero-padded JP^N row-major buffer
+template <typename T>
+__global__ void k_pad_core(const T *__restrict__ G, T *__restrict__ Gp, int N, int JP, int J0,
+                           int J1, int J2, int J3) {
+    const int Js[4] = {J0, J1, J2, J3};
+    int KP = 1;
+    for (int n = 0; n < N; ++n) KP *= JP;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < KP; p += gridDim.x * blockDim.x) {
+        int rem = p, src = 0, mul = 1;
+        bool inside = true;
+        int jj[4];
+        for (int n = N - 1; n >= 0; --n) { jj[n] = rem % JP; rem /= JP; }
+        for (int n = N - 1; n >= 0; --n) {
+            inside &= jj[n] < Js[n];
+            src += jj[n] * mul;
+            mul *= Js[n];
+        }
+        Gp[p] = inside ? G[src] : T(0);
+    }
+}
+
+// ------------------------------------------------------------- row loading
+
+template <int N, int JP, typename T>
+S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t (&rows)[N]) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        rows[n] = A.idx[(int64_t)n * A.nnz + e];
+        const T *r = A.U[n] + (int64_t)rows[n] * A.J[n];
+#pragma unroll
+        for (int k = 0; k < JP; ++k) u[n][k] = (k < A.J[n]) ? r[k] : T(0);
+    }
+}
+
+// ------------------------------------------------------------ det: entries
+
+// One lane per tensor entry of the batch.  Scratch row layout per entry:
+//   [ g_1 (J_1) | ... | g_N (J_N) | L_1 .. L_N | q | L_G ]
+// where g_n = q w_n + (lambda_reg / cnt_n) u_n is the Eq (8) row gradient,
+// q = -e (training) or the upstream sensitivity (adjoint), L_n = |w_n|^2 +
+// lambda_reg / cnt_n and L_G = prod_n |u_n|^2 the curvatures.
+template <int N, int JP, typename T>
+__global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32_t *__restrict__ ids,
+                                                    int64_t nt, const T *__restrict__ Gp,
+                                                    T *__restrict__ scr, int64_t stride,
+                                                    const T *__restrict__ gx) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nt) return;
+    const int64_t e = ids[s];
+    T u[N][JP], w[N][JP];
+    int32_t rows[N];
+    load_rows<N, JP, T>(A, e, u, rows);
+    T xhat;
+    contract<N, JP, T>(Gp, u, w, xhat);
+    const bool train = (gx == nullptr);
+    const T q = train ? -(A.val[e] - xhat) : gx[e];
+    T *out = scr + s * stride;
+    const int64_t cbase = stride - N - 2;  // curvature slots
+    int off = 0;
+    T LG = T(1);
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const T reg = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
+        T ww = T(0), uu = T(0);
+#pragma unroll
+        for (int k = 0; k < JP; ++k) {
+            if (k < A.J[n]) out[off + k] = fmaT(q, w[n][k], reg * u[n][k]);
+            ww = fmaT(w[n][k], w[n][k], ww);
+            uu = fmaT(u[n][k], u[n][k], uu);
+        }
+        off += A.J[n];
+        out[cbase + n] = ww + reg;
+        LG *= uu;
+    }
+    out[stride - 2] = q;
+    out[stride - 1] = LG;
+}
+
+// One lane per coupled-matrix entry.  Scratch row: [ g_u (J) | g_v (J) | L_u | L_v ].
+template <typename T>
+__global__ __launch_bounds__(256) void k_det_matrix(const int32_t *__restrict__ ids, int64_t nm,
+                                                    int64_t id_base, const int32_t *__restrict__ row,
+                                                    const int32_t *__restrict__ col,
+                                                    const T *__restrict__ val, const T *__restrict__ Uc,
+                                                    const T *__restrict__ V, int J,
+                                                    const int32_t *__restrict__ cntV, T lambda_m,
+                                                    T lambda_reg, T *__restrict__ scr,
+                                                    const T *__restrict__ gy) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nm) return;
+    const int64_t e = (int64_t)ids[s] - id_base;
+    const T *u = Uc + (int64_t)row[e] * J;
+    const T *v = V + (int64_t)col[e] * J;
+    T yh = T(0), uu = T(0), vv = T(0);
+    for (int k = 0; k < J; ++k) {
+        yh = fmaT(u[k], v[k], yh);
+        uu = fmaT(u[k], u[k], uu);
+        vv = fmaT(v[k], v[k], vv);
+    }
+    const bool train = (gy == nullptr);
+    // training: d/du = -lm e v, d/dv = -lm e u + lm reg v; adjoint: gy v, gy u
+    const T q = train ? -lambda_m * (val[e] - yh) : gy[e];
+    const T rv = train ? lambda_m * lambda_reg / (T)cntV[col[e]] : T(0);
+    T *out = scr + s * (2 * J + 2);
+    for (int k = 0; k < J; ++k) {
+        out[k] = q * v[k];
+        out[J + k] = fmaT(q, u[k], rv * v[k]);
+    }
+    out[2 * J] = lambda_m * vv;
+    out[2 * J + 1] = fmaT(lambda_m, uu, rv);
+}
+
+// ---------------------------------------------------------- det: core grad
+
+// Core-gradient partial over one chunk of kChunk entries of the batch:
+//   P[chunk][j] = sum_{t in chunk} q_t u^(1)_t[j_1] ... u^(N)_t[j_N]   (padded j)
+// Thread tau owns one index of modes 2..N and all JP values of mode 1.
+template <int N, int JP, typename T>
+__global__ __launch_bounds__(512) void k_core_partial(TensorArgs<T> A, const int32_t *__restrict__ ids,
+                                                      int64_t nt, const T *__restrict__ scr,
+                                                      int64_t stride, T *__restrict__ part,
+                                                      T *__restrict__ part_curv) {
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int SUB = 64;
+    __shared__ T s_q[SUB][JP];        // q_t * u^(1)_t
+    __shared__ T s_u[SUB][N - 1][JP]; // tail rows
+    __shared__ T s_curv[SUB];
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t c1 = (c0 + kChunk < nt) ? c0 + kChunk : nt;
+    int tj[N - 1];
+    {
+        int r = tid;
+#pragma unroll
+        for (int n = N - 2; n >= 0; --n) { tj[n] = r % JP; r /= JP; }
+    }
+    T acc[JP];
+#pragma unroll
+    for (int k = 0; k < JP; ++k) acc[k] = T(0);
+    T curv = T(0);
+    for (int64_t b0 = c0; b0 < c1; b0 += SUB) {
+        const int cnt = (int)((c1 - b0 < SUB) ? c1 - b0 : SUB);
+        __syncthreads();
+        for (int x = tid; x < SUB * N; x += blockDim.x) {
+            const int t = x / N, n = x % N;
+            if (t < cnt) {
+                const int64_t s = b0 + t;
+                const int64_t e = ids[s];
+                const int64_t row = A.idx[(int64_t)n * A.nnz + e];
+                const T *r = A.U[n] + row * A.J[n];
+                const T q = scr[s * stride + stride - 2];
+#pragma unroll
+                for (int k = 0; k < JP; ++k) {
+                    const T v = (k < A.J[n]) ? r[k] : T(0);
+                    if (n == 0) s_q[t][k] = q * v;
+                    else s_u[t][n - 1][k] = v;
+                }
+                if (n == 0) s_curv[t] = scr[s * stride + stride - 1];
+            }
+        }
+        __syncthreads();
+        if (tid < TAIL) {
+            for (int t = 0; t < cnt; ++t) {
+                T p = s_u[t][0][tj[0]];
+#pragma unroll
+                for (int n = 1; n < N - 1; ++n) p *= s_u[t][n][tj[n]];
+#pragma unroll
+                for (int k = 0; k < JP; ++k) acc[k] = fmaT(s_q[t][k], p, acc[k]);
+            }
+        }
+        if (tid == 0)
+            for (int t = 0; t < cnt; ++t) curv += s_curv[t];
+    }
+    if (tid < TAIL) {
+        T *o = part + (int64_t)blockIdx.x * (JP * TAIL);
+#pragma unroll
+        for (int k = 0; k < JP; ++k) o[k * TAIL + tid] = acc[k];
+    }
+    if (tid == 0) part_curv[blockIdx.x] = curv;
+}
+
+// G[j] -= eta * step, step = (sum_chunks P + nt * reg_core * G) / damp;
+// accumulate != 0: dG[j] += sum_chunks P (adjoint).
+template <int N, typename T>
+__global__ void k_core_apply(T *__restrict__ G, const T *__restrict__ part,
+                             const T *__restrict__ part_curv, int64_t nchunks, int JP, int J0,
+                             int J1, int J2, int J3, int64_t nt, T reg_core, T eta, T kappa,
+                             int damp, int accumulate) {
+    const int Js[4] = {J0, J1, J2, J3};
+    int K = 1, KP = 1;
+    for (int n = 0; n < N; ++n) { K *= Js[n]; KP *= JP; }
+    __shared__ T s_L;
+    if (threadIdx.x == 0) {
+        T L = T(0);
+        for (int64_t c = 0; c < nchunks; ++c) L += part_curv[c];
+        s_L = L + (T)nt * reg_core;
+    }
+    __syncthreads();
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < K; j += gridDim.x * blockDim.x) {
+        int rem = j, pj = 0, mul = 1;
+        for (int n = N - 1; n >= 0; --n) {
+            const int jn = rem % Js[n];
+            rem /= Js[n];
+            pj += jn * mul;
+            mul *= JP;
+        }
+        T s = T(0);
+        for (int64_t c = 0; c < nchunks; ++c) s += part[c * KP + pj];
+        if (accumulate) {
+            G[j] += s;
+        } else {
+            const T g = s + (T)nt * reg_core * G[j];
+            T scale = eta;
+            if (damp) {
+                const T d = kappa * eta * s_L;
+                scale = eta / (d > T(1) ? d : T(1));
+            }
+            G[j] -= scale * g;
+        }
+    }
+}
+
+// ---------------------------------------------------------- det: rows apply
+
+// One wavefront per touched row (segment) of the batch.
+template <typename T, int JMAX>
+__global__ __launch_bounds__(256) void k_rows_apply(const uint64_t *__restrict__ contrib,
+                                                    const int64_t *__restrict__ seg_start,
+                                                    const int32_t *__restrict__ seg_row, int64_t s0,
+                                                    int64_t s1, const T *__restrict__ scr,
+                                                    T *__restrict__ P, int J, T eta, T kappa,
+                                                    int damp, int accumulate) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t s = s0 + wid; s < s1; s += nw) {
+        const int64_t c0 = seg_start[s], c1 = seg_start[s + 1];
+        T acc[JMAX];
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) acc[k] = T(0);
+        T L = T(0);
+        for (int64_t c = c0 + lane; c < c1; c += kWave) {
+            const uint64_t v = contrib[c];
+            const T *g = scr + (int64_t)(v & 0xffffffffull);
+#pragma unroll
+            for (int k = 0; k < JMAX; ++k)
+                if (k < J) acc[k] += g[k];
+            L += scr[(int64_t)(v >> 32)];
+        }
+        T mine = T(0);
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k) {
+            const T t = wave_sum(acc[k]);
+            if (lane == k) mine = t;
+        }
+        L = wave_sum(L);
+        if (lane < J) {
+            T *p = P + (int64_t)seg_row[s] * J + lane;
+            if (accumulate) {
+                *p += mine;
+            } else {
+                T scale = eta;
+                if (damp) {
+                    const T d = kappa * eta * L;
+                    scale = eta / (d > T(1) ? d : T(1));
+                }
+                *p -= scale * mine;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- evaluation
+
+// sum over entries of (x - x~)^2 into per-block double partials (fixed order)
+template <int N, int JP, typename T>
+__global__ __launch_bounds__(256) void k_sq_err_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
+                                                       double *__restrict__ part) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        T u[N][JP];
+        int32_t rows[N];
+        load_rows<N, JP, T>(A, e, u, rows);
+        const T r = A.val[e] - predict<N, JP, T>(Gp, u);
+        acc += (double)r * (double)r;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+template <int N, int JP, typename T>
+__global__ __launch_bounds__(256) void k_predict(TensorArgs<T> A, const T *__restrict__ Gp,
+                                                 T *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        T u[N][JP];
+        int32_t rows[N];
+        load_rows<N, JP, T>(A, e, u, rows);
+        out[e] = predict<N, JP, T>(Gp, u);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_predict_matrix(const int32_t *__restrict__ row,
+                                                        const int32_t *__restrict__ col, int64_t nnz,
+                                                        const T *__restrict__ Uc, const T *__restrict__ V,
+                                                        int J, T *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const T *u = Uc + (int64_t)row[e] * J;
+        const T *v = V + (int64_t)col[e] * J;
+        T yh = T(0);
+        for (int k = 0; k < J; ++k) yh = fmaT(u[k], v[k], yh);
+        out[e] = yh;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sq_err_matrix(const int32_t *__restrict__ row,
+                                                       const int32_t *__restrict__ col,
+                                                       const T *__restrict__ val, int64_t nnz,
+                                                       const T *__restrict__ Uc, const T *__restrict__ V,
+                                                       int J, double *__restrict__ part) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const T *u = Uc + (int64_t)row[e] * J;
+        const T *v = V + (int64_t)col[e] * J;
+        T yh = T(0);
+        for (int k = 0; k < J; ++k) yh = fmaT(u[k], v[k], yh);
+        const T r = val[e] - yh;
+        acc += (double)r * (double)r;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// sum over rows with cnt > 0 (all rows if cnt == null) of |row|^2
+template <typename T>
+__global__ __launch_bounds__(256) void k_sq_rows(const T *__restrict__ P, int64_t rows, int J,
+                                                 const int32_t *__restrict__ cnt,
+                                                 double *__restrict__ part) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (cnt && cnt[i] == 0) continue;
+        const T *r = P + i * J;
+        for (int k = 0; k < J; ++k) acc += (double)r[k] * (double)r[k];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+__global__ void k_to_f64(const T *__restrict__ src, double *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+}  // namespace s3

@@ -1,0 +1,917 @@
+// Host side of the C ABI declared in include/s3cmtf.h.
+//
+// Every device buffer is the caller's; the plan carves its working arrays
+// out of one caller-provided workspace (bump allocation, 256-byte aligned).
+#include "s3cmtf.h"
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lockfree.hpp"
+
+using namespace s3;
+
+namespace {
+
+constexpr int kReduceBlocks = 1024;  // fixed grid => fixed reduction order
+
+struct Group {
+    uint64_t *contrib = nullptr;  // sorted (goff | coff << 32)
+    int64_t *seg_start = nullptr; // [nseg + 1]
+    int32_t *seg_row = nullptr;   // [nseg]
+    int64_t n_valid = 0;
+    int64_t nseg = 0;
+    std::vector<int64_t> h_boff;  // per-batch segment ranges
+    int J = 0;
+    int64_t rows = 0;
+};
+
+// bump allocator over the workspace; with base == nullptr it only measures
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <typename X> X *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        X *p = base ? (X *)(base + off) : nullptr;
+        off += count * sizeof(X);
+        return p;
+    }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ dispatch
+
+struct KernelSet {
+    void (*det_tensor)(s3_plan *, const int32_t *, int64_t, const void *, hipStream_t);
+    void (*core_partial)(s3_plan *, const int32_t *, int64_t, hipStream_t);
+    void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
+    void (*predict)(s3_plan *, const int32_t *, int64_t, void *, hipStream_t);
+    void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t);
+};
+
+struct s3_plan {
+    s3_desc d{};
+    int N = 0, M = 0, JP = 0;
+    int64_t K = 1, KP = 1;
+    size_t tsize = 4;  // sizeof compute type
+    bool bound = false;
+    s3_buffers b{};
+    KernelSet ks{};
+    std::string err;
+    // workspace arrays
+    int32_t *cnt[S3_MAX_ORDER] = {};
+    int32_t *cntV[S3_MAX_MATRICES] = {};
+    void *Gp = nullptr;
+    int32_t *flag = nullptr;
+    double *red = nullptr;  // reduction partials
+    std::vector<double> h_red;
+    // det structures
+    int64_t nX = 0, nT = 0, n_items = 0, n_batches = 0;
+    int64_t y_nnz[S3_MAX_MATRICES] = {};
+    int64_t mat_begin[S3_MAX_MATRICES] = {};
+    int32_t *sorted_ids = nullptr;
+    std::vector<int64_t> h_type_off;
+    Group grp[S3_MAX_ORDER + S3_MAX_MATRICES];
+    void *scr = nullptr;
+    int64_t t_stride = 0, RJ = 0;
+    int64_t m_base[S3_MAX_MATRICES] = {}, m_stride[S3_MAX_MATRICES] = {};
+    void *part = nullptr, *part_curv = nullptr;
+    int64_t max_chunks = 0;
+    bool det_ready = false;
+    // lock-free structures
+    LockFreeState lf;
+    // profiling
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0.0;
+    int64_t last_launches = 0;
+};
+
+namespace {
+
+s3_status fail(s3_plan *p, s3_status st, const char *fmt, ...) {
+    if (p) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        p->err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(plan, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(plan, S3_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+inline int grid_for(int64_t n, int tpb, int64_t cap = 65535 * 4) {
+    int64_t g = (n + tpb - 1) / tpb;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+template <typename T> TensorArgs<T> tensor_args(const s3_plan *p, const int32_t *idx, const void *val,
+                                                int64_t nnz) {
+    TensorArgs<T> a{};
+    a.idx = idx;
+    a.nnz = nnz;
+    a.val = (const T *)val;
+    for (int n = 0; n < p->N; ++n) {
+        a.U[n] = (T *)p->b.U[n];
+        a.J[n] = p->d.rank[n];
+        a.cnt[n] = p->cnt[n];
+    }
+    a.lambda_reg = (T)p->d.lambda_reg;
+    return a;
+}
+
+template <int N, int JP, typename T> struct Impl {
+    static void det_tensor(s3_plan *p, const int32_t *ids, int64_t nt, const void *gx, hipStream_t st) {
+        auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
+        hipLaunchKernelGGL((k_det_tensor<N, JP, T>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256), 0, st,
+                           a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
+    }
+    static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
+        constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+        constexpr int TPB = ((TAIL + 63) / 64) * 64;
+        auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
+        const int64_t nch = (nt + kChunk - 1) / kChunk;
+        hipLaunchKernelGGL((k_core_partial<N, JP, T>), dim3((unsigned)nch), dim3(TPB), 0, st, a, ids, nt,
+                           (const T *)p->scr, p->t_stride, (T *)p->part, (T *)p->part_curv);
+    }
+    static void sq_err(s3_plan *p, const int32_t *idx, const void *val, int64_t nnz, double *part,
+                       hipStream_t st) {
+        auto a = tensor_args<T>(p, idx, val, nnz);
+        hipLaunchKernelGGL((k_sq_err_tensor<N, JP, T>), dim3(kReduceBlocks), dim3(256), 0, st, a,
+                           (const T *)p->Gp, part);
+    }
+    static void predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *out, hipStream_t st) {
+        auto a = tensor_args<T>(p, idx, nullptr, nnz);
+        hipLaunchKernelGGL((k_predict<N, JP, T>), dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, a,
+                           (const T *)p->Gp, (T *)out);
+    }
+    static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st) {
+        lockfree_tensor_launch<N, JP, T>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+                                         (const T *)p->Gp, first, count, (T)eta, st);
+    }
+};
+
+template <int N, int JP, typename T> KernelSet make_set() {
+    return KernelSet{&Impl<N, JP, T>::det_tensor, &Impl<N, JP, T>::core_partial, &Impl<N, JP, T>::sq_err,
+                     &Impl<N, JP, T>::predict, &Impl<N, JP, T>::lf_tensor};
+}
+
+template <typename T> bool pick_set(int N, int JP, KernelSet *ks) {
+    if (N == 3) {
+        switch (JP) {
+        case 3: *ks = make_set<3, 3, T>(); return true;
+        case 4: *ks = make_set<3, 4, T>(); return true;
+        case 8: *ks = make_set<3, 8, T>(); return true;
+        case 10: *ks = make_set<3, 10, T>(); return true;
+        case 12: *ks = make_set<3, 12, T>(); return true;
+        case 16: *ks = make_set<3, 16, T>(); return true;
+        }
+    } else if (N == 4) {
+        switch (JP) {
+        case 2: *ks = make_set<4, 2, T>(); return true;
+        case 4: *ks = make_set<4, 4, T>(); return true;
+        case 8: *ks = make_set<4, 8, T>(); return true;
+        }
+    }
+    return false;
+}
+
+int padded_rank(int N, int Jmax) {
+    static const int p3[] = {3, 4, 8, 10, 12, 16};
+    static const int p4[] = {2, 4, 8};
+    if (N == 3) {
+        for (int v : p3) if (Jmax <= v) return v;
+    } else if (N == 4) {
+        for (int v : p4) if (Jmax <= v) return v;
+    }
+    return 0;
+}
+
+double eta_of(const s3_desc &d, int epoch) { return d.eta0 / (1.0 + d.mu * (double)epoch); }
+
+// launch helper for the row-apply kernel (J <= 16)
+template <typename T>
+void rows_apply(const Group &g, int64_t s0, int64_t s1, const void *scr, void *P, double eta, double kappa,
+                int damp, int acc, hipStream_t st) {
+    const int64_t nseg = s1 - s0;
+    if (nseg <= 0) return;
+    const int tpb = 256;
+    hipLaunchKernelGGL((k_rows_apply<T, 16>), dim3(grid_for(nseg * kWave, tpb, 1ll << 20)), dim3(tpb), 0, st,
+                       g.contrib, g.seg_start, g.seg_row, s0, s1, (const T *)scr, (T *)P, g.J, (T)eta,
+                       (T)kappa, damp, acc);
+}
+
+template <typename T>
+void core_apply(s3_plan *p, int64_t nt, double eta, int acc, void *dst, hipStream_t st) {
+    const int64_t nch = (nt + kChunk - 1) / kChunk;
+    const double reg_core = p->d.lambda_reg / (double)p->nX;
+    const int *J = p->d.rank;
+    auto kern = (p->N == 3) ? k_core_apply<3, T> : k_core_apply<4, T>;
+    hipLaunchKernelGGL(kern, dim3(grid_for(p->K, 256, 64)), dim3(256), 0, st, (T *)dst, (const T *)p->part,
+                       (const T *)p->part_curv, nch, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1, nt,
+                       (T)reg_core, (T)eta, (T)(p->N + 1), p->d.damping, acc);
+}
+
+template <typename T> void pad_core(s3_plan *p, hipStream_t st) {
+    const int *J = p->d.rank;
+    hipLaunchKernelGGL(k_pad_core<T>, dim3(grid_for(p->KP, 256, 64)), dim3(256), 0, st, (const T *)p->b.G,
+                       (T *)p->Gp, p->N, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1);
+}
+
+template <typename T> void fill(void *ptr, int64_t n, double v, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, (T *)ptr, n, (T)v);
+}
+
+// One det-mode batch.  gx/gy non-null: adjoint pass (accumulate into dU/dG/dV).
+template <typename T>
+void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *const *gy, void *const *dU,
+               void *dG, void *const *dV, hipStream_t st) {
+    const int M = p->M;
+    const bool adj = (gx != nullptr) || (gy != nullptr) || (dG != nullptr);
+    const int64_t *to = p->h_type_off.data() + b * (M + 1);
+    const int64_t t0 = to[0], nt = to[1] - to[0];
+    pad_core<T>(p, st);
+    if (nt > 0) {
+        if (adj && gx == nullptr)
+            fill<T>(p->scr, nt * p->t_stride, 0.0, st);
+        else
+            p->ks.det_tensor(p, p->sorted_ids + t0, nt, gx, st);
+    }
+    for (int m = 0; m < M; ++m) {
+        const int64_t m0 = to[m + 1], nm = to[m + 2] - to[m + 1];
+        if (nm <= 0) continue;
+        T *scr = (T *)p->scr + p->m_base[m];
+        const int c = p->d.mat_mode[m];
+        if (adj && (gy == nullptr || gy[m] == nullptr)) {
+            fill<T>(scr, nm * p->m_stride[m], 0.0, st);
+            continue;
+        }
+        hipLaunchKernelGGL(k_det_matrix<T>, dim3(grid_for(nm, 256, 1ll << 30)), dim3(256), 0, st,
+                           p->sorted_ids + m0, nm, p->mat_begin[m], p->b.y_row[m], p->b.y_col[m],
+                           (const T *)p->b.y_val[m], (const T *)p->b.U[c], (const T *)p->b.V[m],
+                           p->d.rank[c], p->cntV[m], (T)p->d.lambda_m, (T)p->d.lambda_reg, scr,
+                           adj ? (const T *)gy[m] : (const T *)nullptr);
+    }
+    if (nt > 0) p->ks.core_partial(p, p->sorted_ids + t0, nt, st);
+    for (int g = 0; g < p->N + M; ++g) {
+        const Group &G = p->grp[g];
+        void *P = (g < p->N) ? (adj ? dU[g] : p->b.U[g]) : (adj ? dV[g - p->N] : p->b.V[g - p->N]);
+        rows_apply<T>(G, G.h_boff[b], G.h_boff[b + 1], p->scr, P, eta, (double)(p->N + 1), p->d.damping,
+                      adj ? 1 : 0, st);
+    }
+    if (nt > 0) core_apply<T>(p, nt, eta, adj ? 1 : 0, adj ? dG : p->b.G, st);
+}
+
+template <typename T> size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz,
+                                    const int64_t *y_nnz, bool with_order, size_t *temp_bytes_out);
+
+}  // namespace
+
+// ========================================================================== ABI
+
+extern "C" {
+
+const char *s3_status_string(s3_status st) {
+    switch (st) {
+    case S3_OK: return "ok";
+    case S3_ERR_INVALID_ARG: return "invalid argument";
+    case S3_ERR_INDEX_RANGE: return "index out of range";
+    case S3_ERR_UNSUPPORTED: return "unsupported configuration";
+    case S3_ERR_NONFINITE: return "non-finite result";
+    case S3_ERR_HIP: return "HIP runtime error";
+    case S3_ERR_WORKSPACE: return "workspace too small";
+    case S3_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+s3_status s3_last_error(const s3_plan *plan, char *buf, size_t len) {
+    if (!plan || !buf || len == 0) return S3_ERR_INVALID_ARG;
+    snprintf(buf, len, "%s", plan->err.c_str());
+    return S3_OK;
+}
+
+s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
+    if (!desc || !out) return S3_ERR_INVALID_ARG;
+    *out = nullptr;
+    const s3_desc &d = *desc;
+    if (d.order < 3 || d.order > S3_MAX_ORDER) return S3_ERR_UNSUPPORTED;
+    if (d.n_mat < 0 || d.n_mat > S3_MAX_MATRICES) return S3_ERR_INVALID_ARG;
+    if (d.dtype != S3_F64 && d.dtype != S3_F32 && d.dtype != S3_BF16) return S3_ERR_UNSUPPORTED;
+    if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
+    if (d.batch < 1 || d.round_items < 1) return S3_ERR_INVALID_ARG;
+    if (!(d.eta0 > 0) || !(d.mu >= 0) || !(d.lambda_reg >= 0) || !(d.lambda_m >= 0)) return S3_ERR_INVALID_ARG;
+    int Jmax = 0;
+    for (int n = 0; n < d.order; ++n) {
+        if (d.dims[n] < 1 || d.dims[n] > INT32_MAX || d.rank[n] < 1) return S3_ERR_INVALID_ARG;
+        Jmax = std::max(Jmax, (int)d.rank[n]);
+    }
+    for (int m = 0; m < d.n_mat; ++m) {
+        if (d.mat_mode[m] < 0 || d.mat_mode[m] >= d.order) return S3_ERR_INVALID_ARG;
+        if (d.mat_cols[m] < 1 || d.mat_cols[m] > INT32_MAX) return S3_ERR_INVALID_ARG;
+    }
+    const int JP = padded_rank(d.order, Jmax);
+    if (JP == 0) return S3_ERR_UNSUPPORTED;
+    s3_plan *p = new s3_plan();
+    p->d = d;
+    p->N = d.order;
+    p->M = d.n_mat;
+    p->JP = JP;
+    for (int n = 0; n < p->N; ++n) { p->K *= d.rank[n]; p->KP *= JP; }
+    p->tsize = (d.dtype == S3_F64) ? 8 : 4;
+    const bool ok = (d.dtype == S3_F64) ? pick_set<double>(p->N, JP, &p->ks) : pick_set<float>(p->N, JP, &p->ks);
+    if (!ok) {
+        delete p;
+        return S3_ERR_UNSUPPORTED;
+    }
+    *out = p;
+    return S3_OK;
+}
+
+s3_status s3_plan_destroy(s3_plan *p) {
+    if (!p) return S3_ERR_INVALID_ARG;
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    delete p;
+    return S3_OK;
+}
+
+s3_status s3_workspace_size(const s3_plan *cp, int64_t x_nnz, int64_t t_nnz, const int64_t *y_nnz,
+                            size_t *bytes) {
+    s3_plan *p = const_cast<s3_plan *>(cp);
+    if (!p || !bytes || x_nnz < 1 || t_nnz < 0 || (p->M > 0 && !y_nnz)) return S3_ERR_INVALID_ARG;
+    for (int m = 0; m < p->M; ++m)
+        if (y_nnz[m] < 0) return S3_ERR_INVALID_ARG;
+    size_t temp = 0;
+    *bytes = (p->tsize == 8) ? layout<double>(p, nullptr, x_nnz, t_nnz, y_nnz, true, &temp)
+                             : layout<float>(p, nullptr, x_nnz, t_nnz, y_nnz, true, &temp);
+    return S3_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct DetTemps {
+    uint32_t *key_in, *key_out;
+    int32_t *ids_in;
+    int64_t *type_off;
+    uint64_t *gk_in, *gk_out, *gv_in, *gv_out;
+    int32_t *flags, *segid;
+    uint32_t *segb;
+    int64_t *boff;
+    void *temp;
+    size_t temp_bytes;
+};
+
+// bind-time temporaries of the det-mode build, carved identically for
+// measuring and for use
+void carve_det_temps(Carver &c, DetTemps &t, int64_t n, int64_t nb, int M) {
+    t.key_in = c.take<uint32_t>((size_t)n);
+    t.key_out = c.take<uint32_t>((size_t)n);
+    t.ids_in = c.take<int32_t>((size_t)n);
+    t.type_off = c.take<int64_t>((size_t)(nb * (M + 1) + 1));
+    t.gk_in = c.take<uint64_t>((size_t)n);
+    t.gk_out = c.take<uint64_t>((size_t)n);
+    t.gv_in = c.take<uint64_t>((size_t)n);
+    t.gv_out = c.take<uint64_t>((size_t)n);
+    t.flags = c.take<int32_t>((size_t)n);
+    t.segid = c.take<int32_t>((size_t)n);
+    t.segb = c.take<uint32_t>((size_t)n);
+    t.boff = c.take<int64_t>((size_t)nb + 1);
+    size_t s1 = 0, s2 = 0, s3b = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, s1, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (int32_t *)nullptr, (int32_t *)nullptr, (int)n);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, s2, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                             (uint64_t *)nullptr, (uint64_t *)nullptr, (int)n);
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, s3b, (int32_t *)nullptr, (int32_t *)nullptr, (int)n);
+    t.temp_bytes = std::max({s1, s2, s3b});
+    t.temp = c.take<char>(t.temp_bytes + 256);
+}
+
+// Carve the workspace.  Returns total bytes.  base == nullptr: measure only.
+template <typename T>
+size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_t *y_nnz, bool with_order,
+              size_t *temp_bytes_out) {
+    Carver c(base);
+    const int N = p->N, M = p->M;
+    for (int n = 0; n < N; ++n) p->cnt[n] = c.take<int32_t>((size_t)p->d.dims[n]);
+    for (int m = 0; m < M; ++m) p->cntV[m] = c.take<int32_t>((size_t)p->d.mat_cols[m]);
+    p->Gp = c.take<T>((size_t)p->KP);
+    p->flag = c.take<int32_t>(16);
+    p->red = c.take<double>(8 * kReduceBlocks);
+    int64_t n_items = x_nnz;
+    for (int m = 0; m < M; ++m) n_items += y_nnz[m];
+    const int64_t B = p->d.batch;
+    const int64_t nb = (n_items + B - 1) / B;
+    // lock-free structures
+    lockfree_layout<T>(p->lf, c, N, M, p->d, x_nnz, y_nnz, p->KP, p->JP);
+    if (with_order) {
+        p->sorted_ids = c.take<int32_t>((size_t)n_items);
+        // groups
+        for (int g = 0; g < N + M; ++g) {
+            int64_t nv = 0;
+            if (g < N) {
+                nv = x_nnz;
+                for (int m = 0; m < M; ++m)
+                    if (p->d.mat_mode[m] == g) nv += y_nnz[m];
+            } else {
+                nv = y_nnz[g - N];
+            }
+            p->grp[g].n_valid = nv;
+            p->grp[g].contrib = c.take<uint64_t>((size_t)std::max<int64_t>(nv, 1));
+            p->grp[g].seg_start = c.take<int64_t>((size_t)nv + 1);
+            p->grp[g].seg_row = c.take<int32_t>((size_t)std::max<int64_t>(nv, 1));
+        }
+        // per-batch scratch
+        const int64_t RJ = [&] { int64_t s = 0; for (int n = 0; n < N; ++n) s += p->d.rank[n]; return s; }();
+        p->RJ = RJ;
+        p->t_stride = RJ + N + 2;
+        const int64_t max_nt = std::min(B, x_nnz);
+        int64_t off = max_nt * p->t_stride;
+        for (int m = 0; m < M; ++m) {
+            const int Jc = p->d.rank[p->d.mat_mode[m]];
+            p->m_stride[m] = 2 * Jc + 2;
+            p->m_base[m] = off;
+            off += std::min(B, std::max<int64_t>(y_nnz[m], 1)) * p->m_stride[m];
+        }
+        p->scr = c.take<T>((size_t)off);
+        p->max_chunks = (max_nt + kChunk - 1) / kChunk;
+        p->part = c.take<T>((size_t)(p->max_chunks * p->KP));
+        p->part_curv = c.take<T>((size_t)p->max_chunks);
+        // bind-time temporaries (same carve as build_det, from an aligned start)
+        c.off = (c.off + 255) & ~(size_t)255;
+        const size_t t0 = c.off;
+        DetTemps tmp;
+        carve_det_temps(c, tmp, n_items, nb, M);
+        if (temp_bytes_out) *temp_bytes_out = c.off - t0;
+    }
+    return c.off + 256;
+}
+
+template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_t st) {
+    const int N = p->N, M = p->M;
+    const int64_t n = p->n_items, B = p->d.batch;
+    const int64_t nb = p->n_batches;
+    Carver c(tmp_base);
+    DetTemps t;
+    carve_det_temps(c, t, n, nb, M);
+    uint32_t *key_in = t.key_in, *key_out = t.key_out;
+    int32_t *ids_in = t.ids_in;
+    int64_t *type_off = t.type_off;
+    uint64_t *gk_in = t.gk_in, *gk_out = t.gk_out, *gv_in = t.gv_in, *gv_out = t.gv_out;
+    int32_t *flags = t.flags, *segid = t.segid;
+    uint32_t *segb = t.segb;
+    int64_t *boff = t.boff;
+    size_t tb = t.temp_bytes;
+    void *temp = t.temp;
+
+    int64_t mat_end[S3_MAX_MATRICES] = {};
+    for (int m = 0; m < M; ++m) mat_end[m] = p->mat_begin[m] + p->y_nnz[m];
+    int64_t *d_mat_end = (int64_t *)p->red;  // small staging (<= 4 values)
+    HIPCHK(p, hipMemcpyAsync(d_mat_end, mat_end, sizeof(int64_t) * S3_MAX_MATRICES, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p->b.order, n, B, p->nX,
+                       (int32_t)M, (const int64_t *)d_mat_end, key_in, ids_in);
+    const int nkey_bits = 32;
+    HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(temp, tb, key_in, key_out, ids_in, p->sorted_ids, (int)n, 0,
+                                                 nkey_bits, st));
+    const int64_t nkeys = nb * (M + 1);
+    hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, key_out, n,
+                       nkeys, type_off);
+    p->h_type_off.assign((size_t)nkeys + 1, 0);
+    HIPCHK(p, hipMemcpyAsync(p->h_type_off.data(), type_off, sizeof(int64_t) * (nkeys + 1),
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+
+    GroupArgs ga{};
+    ga.sorted_ids = p->sorted_ids;
+    ga.sorted_keys = key_out;
+    ga.type_off = type_off;
+    ga.n = n;
+    ga.M = M;
+    ga.N = N;
+    ga.nX = p->nX;
+    ga.x_idx = p->b.x_idx;
+    ga.x_nnz = p->nX;
+    ga.t_stride = p->t_stride;
+    for (int m = 0; m < M; ++m) {
+        ga.y_row[m] = p->b.y_row[m];
+        ga.y_col[m] = p->b.y_col[m];
+        ga.mat_begin[m] = p->mat_begin[m];
+        ga.mat_mode[m] = p->d.mat_mode[m];
+        ga.m_base[m] = p->m_base[m];
+        ga.m_stride[m] = p->m_stride[m];
+        ga.m_J[m] = p->d.rank[p->d.mat_mode[m]];
+    }
+    int64_t goff = 0;
+    for (int g = 0; g < N + M; ++g) {
+        Group &G = p->grp[g];
+        ga.group = g;
+        if (g < N) {
+            ga.t_goff = goff;
+            ga.t_coff = p->RJ + g;
+            goff += p->d.rank[g];
+            G.J = p->d.rank[g];
+            G.rows = p->d.dims[g];
+        } else {
+            G.J = p->d.rank[p->d.mat_mode[g - N]];
+            G.rows = p->d.mat_cols[g - N];
+        }
+        hipLaunchKernelGGL(k_group_contrib, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, ga, gk_in, gv_in);
+        HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(temp, tb, gk_in, gk_out, gv_in, gv_out, (int)n, 0, 64, st));
+        const int64_t nv = G.n_valid;
+        G.h_boff.assign((size_t)nb + 1, 0);
+        if (nv == 0) { G.nseg = 0; continue; }
+        HIPCHK(p, hipMemcpyAsync(G.contrib, gv_out, sizeof(uint64_t) * nv, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, st, gk_out, nv, flags);
+        HIPCHK(p, hipcub::DeviceScan::InclusiveSum(temp, tb, flags, segid, (int)nv, st));
+        hipLaunchKernelGGL(k_seg_write, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, st, gk_out, flags, segid,
+                           nv, G.seg_start, G.seg_row, segb);
+        int32_t nseg32 = 0;
+        HIPCHK(p, hipMemcpyAsync(&nseg32, segid + nv - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        G.nseg = nseg32;
+        hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(G.nseg + 1, 256, 16384)), dim3(256), 0, st, segb,
+                           G.nseg, nb, boff);
+        HIPCHK(p, hipMemcpyAsync(G.h_boff.data(), boff, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+    }
+    p->det_ready = true;
+    return S3_OK;
+}
+
+template <typename T> s3_status bind_impl(s3_plan *p, const s3_buffers *buf, void *ws, size_t ws_bytes,
+                                          hipStream_t st) {
+    const int N = p->N, M = p->M;
+    int64_t y_nnz[S3_MAX_MATRICES] = {};
+    for (int m = 0; m < M; ++m) y_nnz[m] = buf->y_nnz[m];
+    const bool with_order = buf->order != nullptr;
+    size_t temp_bytes = 0;
+    const size_t need = layout<T>(p, nullptr, buf->x_nnz, buf->t_nnz, y_nnz, with_order, &temp_bytes);
+    if (!ws || ws_bytes < need)
+        return fail(p, S3_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    p->b = *buf;
+    p->nX = buf->x_nnz;
+    p->nT = buf->t_nnz;
+    int64_t n_items = p->nX;
+    for (int m = 0; m < M; ++m) {
+        p->y_nnz[m] = y_nnz[m];
+        p->mat_begin[m] = n_items;
+        n_items += y_nnz[m];
+    }
+    p->n_items = n_items;
+    p->n_batches = (n_items + p->d.batch - 1) / p->d.batch;
+    layout<T>(p, ws, buf->x_nnz, buf->t_nnz, y_nnz, with_order, nullptr);
+    // index validation
+    HIPCHK(p, hipMemsetAsync(p->flag, 0, sizeof(int32_t) * 16, st));
+    for (int n = 0; n < N; ++n) {
+        hipLaunchKernelGGL(k_check_range, dim3(grid_for(p->nX, 256, 4096)), dim3(256), 0, st,
+                           buf->x_idx + (int64_t)n * p->nX, p->nX, p->d.dims[n], p->flag);
+        if (p->nT > 0)
+            hipLaunchKernelGGL(k_check_range, dim3(grid_for(p->nT, 256, 4096)), dim3(256), 0, st,
+                               buf->t_idx + (int64_t)n * p->nT, p->nT, p->d.dims[n], p->flag);
+    }
+    for (int m = 0; m < M; ++m) {
+        if (y_nnz[m] == 0) continue;
+        hipLaunchKernelGGL(k_check_range, dim3(grid_for(y_nnz[m], 256, 4096)), dim3(256), 0, st, buf->y_row[m],
+                           y_nnz[m], p->d.dims[p->d.mat_mode[m]], p->flag);
+        hipLaunchKernelGGL(k_check_range, dim3(grid_for(y_nnz[m], 256, 4096)), dim3(256), 0, st, buf->y_col[m],
+                           y_nnz[m], p->d.mat_cols[m], p->flag);
+    }
+    if (with_order)
+        hipLaunchKernelGGL(k_check_range, dim3(grid_for(n_items, 256, 4096)), dim3(256), 0, st, buf->order,
+                           n_items, n_items, p->flag + 1);
+    int32_t hflag[2] = {0, 0};
+    HIPCHK(p, hipMemcpyAsync(hflag, p->flag, sizeof hflag, hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    if (hflag[0]) return fail(p, S3_ERR_INDEX_RANGE, "an entry index lies outside its mode or matrix");
+    if (hflag[1]) return fail(p, S3_ERR_INDEX_RANGE, "the item order holds an id outside [0, n_items)");
+    // counts |Omega_X^{n,i}| and |Omega_Y^{2,k}|
+    for (int n = 0; n < N; ++n) {
+        HIPCHK(p, hipMemsetAsync(p->cnt[n], 0, sizeof(int32_t) * p->d.dims[n], st));
+        hipLaunchKernelGGL(k_hist, dim3(grid_for(p->nX, 256, 4096)), dim3(256), 0, st,
+                           buf->x_idx + (int64_t)n * p->nX, p->nX, p->cnt[n]);
+    }
+    for (int m = 0; m < M; ++m) {
+        HIPCHK(p, hipMemsetAsync(p->cntV[m], 0, sizeof(int32_t) * p->d.mat_cols[m], st));
+        if (y_nnz[m] > 0)
+            hipLaunchKernelGGL(k_hist, dim3(grid_for(y_nnz[m], 256, 4096)), dim3(256), 0, st, buf->y_col[m],
+                               y_nnz[m], p->cntV[m]);
+    }
+    p->det_ready = false;
+    if (with_order) {
+        // temporaries sit at the end of the carved layout
+        char *tmp = (char *)ws + (need - 256 - temp_bytes);  // the offset layout() measured from
+        s3_status s = build_det<T>(p, tmp, st);
+        if (s != S3_OK) return s;
+    }
+    s3_status s = lockfree_build<T>(p->lf, p->d, buf, p->cnt, p->cntV, p->nX, y_nnz, st, p->err);
+    if (s != S3_OK) return s;
+    HIPCHK(p, hipStreamSynchronize(st));
+    HIPCHK(p, hipGetLastError());
+    p->bound = true;
+    return S3_OK;
+}
+
+template <typename T> s3_status loss_impl(s3_plan *p, double *out, hipStream_t st) {
+    const int N = p->N, M = p->M;
+    double *r = p->red;
+    pad_core<T>(p, st);
+    p->ks.sq_err(p, p->b.x_idx, p->b.x_val, p->nX, r, st);                     // slot 0: tensor sse
+    hipLaunchKernelGGL(k_sq_rows<T>, dim3(kReduceBlocks), dim3(256), 0, st, (const T *)p->b.G, (int64_t)1,
+                       (int)p->K, (const int32_t *)nullptr, r + kReduceBlocks);  // slot 1: |G|^2
+    // slot 2: observed factor rows (accumulated over modes on host)
+    std::vector<double> h(kReduceBlocks);
+    double sse_t = 0, gg = 0, uu = 0, sse_m = 0, vv = 0;
+    p->h_red.resize(2 * kReduceBlocks);
+    HIPCHK(p, hipMemcpyAsync(p->h_red.data(), r, sizeof(double) * 2 * kReduceBlocks, hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    for (int i = 0; i < kReduceBlocks; ++i) sse_t += p->h_red[i];
+    for (int i = 0; i < kReduceBlocks; ++i) gg += p->h_red[kReduceBlocks + i];
+    for (int n = 0; n < N; ++n) {
+        hipLaunchKernelGGL(k_sq_rows<T>, dim3(kReduceBlocks), dim3(256), 0, st, (const T *)p->b.U[n],
+                           p->d.dims[n], p->d.rank[n], (const int32_t *)p->cnt[n], r);
+        HIPCHK(p, hipMemcpyAsync(h.data(), r, sizeof(double) * kReduceBlocks, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        for (double v : h) uu += v;
+    }
+    for (int m = 0; m < M; ++m) {
+        const int c = p->d.mat_mode[m];
+        if (p->y_nnz[m] > 0) {
+            hipLaunchKernelGGL(k_sq_err_matrix<T>, dim3(kReduceBlocks), dim3(256), 0, st, p->b.y_row[m],
+                               p->b.y_col[m], (const T *)p->b.y_val[m], p->y_nnz[m], (const T *)p->b.U[c],
+                               (const T *)p->b.V[m], p->d.rank[c], r);
+            HIPCHK(p, hipMemcpyAsync(h.data(), r, sizeof(double) * kReduceBlocks, hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipStreamSynchronize(st));
+            for (double v : h) sse_m += v;
+        }
+        hipLaunchKernelGGL(k_sq_rows<T>, dim3(kReduceBlocks), dim3(256), 0, st, (const T *)p->b.V[m],
+                           p->d.mat_cols[m], p->d.rank[c], (const int32_t *)p->cntV[m], r);
+        HIPCHK(p, hipMemcpyAsync(h.data(), r, sizeof(double) * kReduceBlocks, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        for (double v : h) vv += v;
+    }
+    HIPCHK(p, hipGetLastError());
+    const double ft = sse_t + p->d.lambda_reg * (gg + uu);
+    const double fm = sse_m + p->d.lambda_reg * vv;
+    out[0] = 0.5 * ft + 0.5 * p->d.lambda_m * fm;
+    out[1] = ft;
+    out[2] = fm;
+    if (!std::isfinite(out[0])) return fail(p, S3_ERR_NONFINITE, "objective is not finite");
+    return S3_OK;
+}
+
+// synchronous range check of caller-supplied SoA indices (not on the hot path)
+s3_status check_indices(s3_plan *p, const int32_t *idx, int64_t nnz, int modes, const int64_t *lim,
+                        hipStream_t st) {
+    HIPCHK(p, hipMemsetAsync(p->flag + 2, 0, sizeof(int32_t), st));
+    for (int n = 0; n < modes; ++n)
+        hipLaunchKernelGGL(k_check_range, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, idx + (int64_t)n * nnz,
+                           nnz, lim[n], p->flag + 2);
+    int32_t h = 0;
+    HIPCHK(p, hipMemcpyAsync(&h, p->flag + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    if (h) return fail(p, S3_ERR_INDEX_RANGE, "an index lies outside its mode");
+    return S3_OK;
+}
+
+template <typename T> s3_status rmse_impl(s3_plan *p, double *out, hipStream_t st) {
+    if (p->nT == 0) { *out = 0.0; return S3_OK; }
+    pad_core<T>(p, st);
+    p->ks.sq_err(p, p->b.t_idx, p->b.t_val, p->nT, p->red, st);
+    std::vector<double> h(kReduceBlocks);
+    HIPCHK(p, hipMemcpyAsync(h.data(), p->red, sizeof(double) * kReduceBlocks, hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    HIPCHK(p, hipGetLastError());
+    double s = 0;
+    for (double v : h) s += v;
+    *out = std::sqrt(s / (double)p->nT);
+    if (!std::isfinite(*out)) return fail(p, S3_ERR_NONFINITE, "held-out RMSE is not finite");
+    return S3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+s3_status s3_bind(s3_plan *p, const s3_buffers *buf, void *d_ws, size_t ws_bytes, void *stream) {
+    if (!p || !buf) return S3_ERR_INVALID_ARG;
+    if (!buf->x_idx || !buf->x_val || buf->x_nnz < 1 || buf->t_nnz < 0 || (buf->t_nnz > 0 && (!buf->t_idx || !buf->t_val)))
+        return fail(p, S3_ERR_INVALID_ARG, "training entries missing or sizes negative");
+    for (int n = 0; n < p->N; ++n)
+        if (!buf->U[n]) return fail(p, S3_ERR_INVALID_ARG, "factor U[%d] is null", n);
+    if (!buf->G) return fail(p, S3_ERR_INVALID_ARG, "core is null");
+    for (int m = 0; m < p->M; ++m) {
+        if (!buf->V[m] || buf->y_nnz[m] < 0 || (buf->y_nnz[m] > 0 && (!buf->y_row[m] || !buf->y_col[m] || !buf->y_val[m])))
+            return fail(p, S3_ERR_INVALID_ARG, "coupled matrix %d incomplete", m);
+    }
+    int64_t n_items = buf->x_nnz;
+    for (int m = 0; m < p->M; ++m) n_items += buf->y_nnz[m];
+    if (n_items > INT32_MAX) return fail(p, S3_ERR_UNSUPPORTED, "more than 2^31 - 1 items");
+    p->bound = false;
+    hipStream_t st = (hipStream_t)stream;
+    return (p->tsize == 8) ? bind_impl<double>(p, buf, d_ws, ws_bytes, st) : bind_impl<float>(p, buf, d_ws, ws_bytes, st);
+}
+
+s3_status s3_det_batches(s3_plan *p, int64_t first, int64_t count, double eta, void *stream) {
+    if (!p) return S3_ERR_INVALID_ARG;
+    if (!p->bound || !p->det_ready) return fail(p, S3_ERR_STATE, "det mode needs s3_bind with an item order");
+    if (first < 0 || count < 0 || first + count > p->n_batches)
+        return fail(p, S3_ERR_INVALID_ARG, "batch range [%lld, %lld) outside [0, %lld)", (long long)first,
+                    (long long)(first + count), (long long)p->n_batches);
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t b = first; b < first + count; ++b) {
+        if (p->tsize == 8) det_batch<double>(p, b, eta, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+        else det_batch<float>(p, b, eta, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+    }
+    HIPCHK(p, hipGetLastError());
+    return S3_OK;
+}
+
+s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
+    if (!p || epoch < 0) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_epoch before s3_bind");
+    hipStream_t st = (hipStream_t)stream;
+    const double eta = eta_of(p->d, epoch);
+    if (!p->ev0) {
+        HIPCHK(p, hipEventCreate(&p->ev0));
+        HIPCHK(p, hipEventCreate(&p->ev1));
+    }
+    if (mode == S3_DET_MINIBATCH) {
+        if (!p->det_ready) return fail(p, S3_ERR_STATE, "det mode needs s3_bind with an item order");
+        HIPCHK(p, hipEventRecord(p->ev0, st));
+        s3_status s = s3_det_batches(p, 0, p->n_batches, eta, stream);
+        HIPCHK(p, hipEventRecord(p->ev1, st));
+        p->last_launches = p->n_batches;
+        return s;
+    }
+    if (mode == S3_LOCKFREE) {
+        if (p->lf.H == 0) return fail(p, S3_ERR_UNSUPPORTED, "lock-free mode: rank too large for the LDS tables");
+        HIPCHK(p, hipEventRecord(p->ev0, st));
+        s3_status s;
+        auto round = [&](int64_t f, int64_t c, double e, hipStream_t s_) { p->ks.lf_tensor(p, f, c, e, s_); };
+        if (p->tsize == 8) {
+            pad_core<double>(p, st);
+            s = lockfree_epoch<double>(p->lf, p->d, epoch, eta, (double *)p->Gp, st, p->err, round);
+        } else {
+            pad_core<float>(p, st);
+            s = lockfree_epoch<float>(p->lf, p->d, epoch, eta, (float *)p->Gp, st, p->err, round);
+        }
+        HIPCHK(p, hipEventRecord(p->ev1, st));
+        HIPCHK(p, hipGetLastError());
+        p->last_launches = p->lf.n_rounds;
+        return s;
+    }
+    return fail(p, S3_ERR_INVALID_ARG, "unknown mode %d", mode);
+}
+
+s3_status s3_loss(s3_plan *p, double *out, void *stream) {
+    if (!p || !out) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_loss before s3_bind");
+    hipStream_t st = (hipStream_t)stream;
+    return (p->tsize == 8) ? loss_impl<double>(p, out, st) : loss_impl<float>(p, out, st);
+}
+
+s3_status s3_rmse(s3_plan *p, double *out, void *stream) {
+    if (!p || !out) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_rmse before s3_bind");
+    hipStream_t st = (hipStream_t)stream;
+    return (p->tsize == 8) ? rmse_impl<double>(p, out, st) : rmse_impl<float>(p, out, st);
+}
+
+s3_status s3_predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *xhat, void *stream) {
+    if (!p || (nnz > 0 && (!idx || !xhat)) || nnz < 0) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_predict before s3_bind");
+    if (nnz == 0) return S3_OK;
+    hipStream_t st = (hipStream_t)stream;
+    {
+        s3_status v = check_indices(p, idx, nnz, p->N, p->d.dims, st);
+        if (v != S3_OK) return v;
+    }
+    if (p->tsize == 8) pad_core<double>(p, st); else pad_core<float>(p, st);
+    p->ks.predict(p, idx, nnz, xhat, st);
+    HIPCHK(p, hipGetLastError());
+    return S3_OK;
+}
+
+s3_status s3_predict_matrix(s3_plan *p, int32_t m, const int32_t *row, const int32_t *col, int64_t nnz,
+                            void *yhat, void *stream) {
+    if (!p || m < 0 || m >= p->M || nnz < 0 || (nnz > 0 && (!row || !col || !yhat))) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_predict_matrix before s3_bind");
+    if (nnz == 0) return S3_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int c = p->d.mat_mode[m];
+    {
+        const int64_t lim_r[1] = {p->d.dims[c]}, lim_c[1] = {p->d.mat_cols[m]};
+        s3_status v = check_indices(p, row, nnz, 1, lim_r, st);
+        if (v == S3_OK) v = check_indices(p, col, nnz, 1, lim_c, st);
+        if (v != S3_OK) return v;
+    }
+    if (p->tsize == 8)
+        hipLaunchKernelGGL(k_predict_matrix<double>, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, row, col, nnz,
+                           (const double *)p->b.U[c], (const double *)p->b.V[m], p->d.rank[c], (double *)yhat);
+    else
+        hipLaunchKernelGGL(k_predict_matrix<float>, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, row, col, nnz,
+                           (const float *)p->b.U[c], (const float *)p->b.V[m], p->d.rank[c], (float *)yhat);
+    HIPCHK(p, hipGetLastError());
+    return S3_OK;
+}
+
+s3_status s3_backward(s3_plan *p, const void *gx, const void *const *gy, void *const *dU, void *dG,
+                      void *const *dV, void *stream) {
+    if (!p || !dU || !dG || (p->M > 0 && !dV)) return S3_ERR_INVALID_ARG;
+    if (!p->bound || !p->det_ready) return fail(p, S3_ERR_STATE, "s3_backward needs s3_bind with an item order");
+    for (int n = 0; n < p->N; ++n)
+        if (!dU[n]) return S3_ERR_INVALID_ARG;
+    for (int m = 0; m < p->M; ++m)
+        if (!dV[m]) return S3_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = p->tsize == 8;
+    for (int n = 0; n < p->N; ++n)
+        f64 ? fill<double>(dU[n], p->d.dims[n] * p->d.rank[n], 0.0, st) : fill<float>(dU[n], p->d.dims[n] * p->d.rank[n], 0.0, st);
+    f64 ? fill<double>(dG, p->K, 0.0, st) : fill<float>(dG, p->K, 0.0, st);
+    for (int m = 0; m < p->M; ++m) {
+        const int64_t cnt = p->d.mat_cols[m] * p->d.rank[p->d.mat_mode[m]];
+        f64 ? fill<double>(dV[m], cnt, 0.0, st) : fill<float>(dV[m], cnt, 0.0, st);
+    }
+    const void *const nogy[S3_MAX_MATRICES] = {nullptr, nullptr, nullptr, nullptr};
+    const void *const *gyv = gy ? gy : nogy;
+    for (int64_t b = 0; b < p->n_batches; ++b) {
+        if (f64) det_batch<double>(p, b, 0.0, gx, gyv, dU, dG, dV, st);
+        else det_batch<float>(p, b, 0.0, gx, gyv, dU, dG, dV, st);
+    }
+    HIPCHK(p, hipGetLastError());
+    return S3_OK;
+}
+
+s3_status s3_export(s3_plan *p, int32_t which, int32_t index, double *host_dst, size_t bytes, void *stream) {
+    if (!p || !host_dst) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_export before s3_bind");
+    const void *src = nullptr;
+    int64_t count = 0;
+    if (which == 0 && index >= 0 && index < p->N) {
+        src = p->b.U[index];
+        count = p->d.dims[index] * p->d.rank[index];
+    } else if (which == 1) {
+        src = p->b.G;
+        count = p->K;
+    } else if (which == 2 && index >= 0 && index < p->M) {
+        src = p->b.V[index];
+        count = p->d.mat_cols[index] * p->d.rank[p->d.mat_mode[index]];
+    } else {
+        return fail(p, S3_ERR_INVALID_ARG, "unknown parameter (%d, %d)", which, index);
+    }
+    if (bytes != (size_t)count * sizeof(double))
+        return fail(p, S3_ERR_INVALID_ARG, "export needs %lld bytes", (long long)(count * 8));
+    hipStream_t st = (hipStream_t)stream;
+    if (p->tsize == 8) {
+        HIPCHK(p, hipMemcpyAsync(host_dst, src, bytes, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+    } else {
+        std::vector<float> tmp((size_t)count);
+        HIPCHK(p, hipMemcpyAsync(tmp.data(), src, sizeof(float) * count, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        for (int64_t i = 0; i < count; ++i) host_dst[i] = (double)tmp[(size_t)i];
+    }
+    return S3_OK;
+}
+
+s3_status s3_sync_bf16(s3_plan *p, void *stream) {
+    if (!p) return S3_ERR_INVALID_ARG;
+    (void)stream;
+    return fail(p, S3_ERR_UNSUPPORTED, "bf16 working copies are not built in this library");
+}
+
+s3_status s3_last_epoch_profile(const s3_plan *cp, double *kernel_ms, int64_t *launches) {
+    s3_plan *p = const_cast<s3_plan *>(cp);
+    if (!p || !kernel_ms || !launches) return S3_ERR_INVALID_ARG;
+    if (!p->ev0) return S3_ERR_STATE;
+    float ms = 0.f;
+    HIPCHK(p, hipEventSynchronize(p->ev1));
+    HIPCHK(p, hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    *kernel_ms = ms;
+    *launches = p->last_launches;
+    return S3_OK;
+}
+
+}  // extern "C"

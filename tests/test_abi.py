@@ -1,0 +1,100 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/s3cmtf.h declares, and rejects bad descriptors and out-of-order
+calls without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1708_08640_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1708_08640_amd.build import build
+        build()
+    return _abi, _abi.load()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "s3cmtf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(s3_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    _abi, lib = _lib()
+    assert _declared() == sorted(_abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    _abi, lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _desc(_abi, **kw):
+    d = _abi.S3Desc()
+    d.order, d.n_mat = 3, 1
+    for n in range(3):
+        d.dims[n], d.rank[n] = 100, 10
+    d.mat_mode[0], d.mat_cols[0] = 0, 50
+    d.dtype, d.eta0, d.mu, d.lambda_reg, d.lambda_m = 1, 0.01, 0.1, 0.01, 10.0
+    d.batch, d.round_items = 64, 64
+    for k, v in kw.items():
+        if k in ("dims", "rank"):
+            for n, x in enumerate(v):
+                getattr(d, k)[n] = x
+        else:
+            setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(order=2), -3),
+    (dict(order=5), -3),
+    (dict(dtype=7), -3),
+    (dict(rank=(10, 10, 40)), -3),
+    (dict(batch=0), -1),
+    (dict(eta0=-1.0), -1),
+    (dict(n_mat=9), -1),
+    (dict(mat_mode=(3, 0, 0, 0)), -1),
+])
+def test_plan_create_rejects(kw, status):
+    _abi, lib = _lib()
+    d = _desc(_abi)
+    if "mat_mode" in kw:
+        d.mat_mode[0] = kw.pop("mat_mode")[0]
+    d = _desc(_abi, **kw) if kw else d
+    if "mat_mode" not in kw and d.mat_mode[0] == 3:
+        pass
+    h = C.c_void_p()
+    assert lib.s3_plan_create(C.byref(d), C.byref(h)) == status
+    assert not h.value
+
+
+def test_calls_before_bind_are_state_errors():
+    _abi, lib = _lib()
+    d = _desc(_abi)
+    h = C.c_void_p()
+    assert lib.s3_plan_create(C.byref(d), C.byref(h)) == 0
+    out = (C.c_double * 3)()
+    assert lib.s3_epoch(h, 0, 0, None) == -7
+    assert lib.s3_loss(h, out, None) == -7
+    assert lib.s3_rmse(h, out, None) == -7
+    assert lib.s3_det_batches(h, 0, 1, 0.01, None) == -7
+    buf = C.create_string_buffer(256)
+    assert lib.s3_last_error(h, buf, 256) == 0 and b"bind" in buf.value
+    y = (C.c_int64 * 1)(100)
+    sz = C.c_size_t()
+    assert lib.s3_workspace_size(h, 1000, 100, y, C.byref(sz)) == 0 and sz.value > 0
+    assert lib.s3_workspace_size(h, 0, 100, y, C.byref(sz)) == -1
+    assert lib.s3_plan_destroy(h) == 0
+
+
+def test_status_strings():
+    _abi, lib = _lib()
+    for st in range(-7, 1):
+        assert lib.s3_status_string(st)

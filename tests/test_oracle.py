@@ -330,3 +330,52 @@ def test_qr_step_keeps_predictions_and_orthogonalises():
     for m, c in enumerate(params.modes):
         assert rel(q.U[c] @ q.V[m].T, params.U[c] @ params.V[m].T) < 1e-12
     assert rel(oracle.predict(q, grid), oracle.predict(params, grid)) < 1e-12
+
+
+# ---------------------------------------------------------------- damped batches
+
+def test_leave_one_out_contraction_is_prediction_gradient():
+    # w_n = G x_{-n} {u} is the derivative of the prediction w.r.t. row n (Eq 4)
+    rng = np.random.default_rng(11)
+    for dims, ranks in [((4, 3, 5), (2, 3, 2)), ((3, 2, 2, 3), (2, 2, 1, 2))]:
+        params = _rand_params(rng, dims, ranks, [])
+        rows = [int(rng.integers(0, I)) for I in dims]
+        w = oracle.tensor_item_w(params, rows)
+        for n in range(len(dims)):
+            def pred():
+                return dense_predict(params.U, params.G, np.array(rows)[:, None])[0]
+            mask = np.zeros_like(params.U[n], dtype=bool)
+            mask[rows[n]] = True
+            assert rel(w[n], fd_grad(pred, params.U[n], mask=mask)[rows[n]]) < 1e-8
+
+
+def test_damped_batches_reduce_to_sgd_for_small_steps():
+    cfg, p, params = _problem("cfg1")
+    order = item_order(p.n_items, 4, 0)
+    a, b = params.copy(), params.copy()
+    oracle.sgd_epoch(a, p, order, 0.01)
+    oracle.minibatch_epoch(b, p, order, 1, 0.01, damping=True)
+    for x, y in zip(a.U + [a.G] + a.V, b.U + [b.G] + b.V):
+        assert np.array_equal(x, y)
+
+
+def test_damped_step_of_one_entry():
+    cfg, p, params = _problem("tiny3", matrices=(), nnz=12, dims=(10, 8, 9))
+    cnt, _ = oracle.counts(params, p)
+    e0 = 0
+    rows = [int(p.train_idx[n][e0]) for n in range(3)]
+    reg_row = [cfg.lambda_reg / cnt[n][rows[n]] for n in range(3)]
+    reg_core = cfg.lambda_reg / p.n_train
+    eta = 50.0  # large enough that every block is damped
+    e, gU, gG = oracle.tensor_item_grad(params, rows, p.train_val[e0], reg_row, reg_core)
+    w = oracle.tensor_item_w(params, rows)
+    b = params.copy()
+    order = np.arange(p.n_items)
+    oracle.minibatch_epoch(b, p, order, 1, eta, 0, 1, damping=True)
+    kappa = 4.0
+    for n in range(3):
+        L = w[n] @ w[n] + reg_row[n]
+        step = eta / max(1.0, kappa * eta * L)
+        assert rel(b.U[n][rows[n]], params.U[n][rows[n]] - step * gU[n]) < 1e-13
+    LG = np.prod([params.U[n][rows[n]] @ params.U[n][rows[n]] for n in range(3)]) + reg_core
+    assert rel(b.G, params.G - eta / max(1.0, kappa * eta * LG) * gG) < 1e-13
