@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: tensor + coupled-matrix nonzero updates per second per epoch, at
+a fixed held-out RMSE, on one MI355X.
+
+Workload (default): the 3-way 1M x 100K x 100 tensor with 10M Zipf(1.2)
+entries (9M train / 1M held out), Tucker core 10x10x10, one coupled 1M x 1M
+matrix with 5M entries on mode 1; FP32; lock-free mode.  One "step" is one
+epoch: every training tensor entry and every matrix entry updated once.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tensor+matrix nonzero updates/sec per epoch at fixed held-out RMSE, 1 GPU"
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def tensor_entry_flops(ranks):
+    """Algorithmic FP operations of one tensor entry: 4K for the single-pass
+    contraction (x~ and every leave-one-out vector), 2K for its share of the
+    core gradient, and 10 per factor-row element for gradients, curvatures
+    and the update (K = prod J)."""
+    K = 1
+    for j in ranks:
+        K *= j
+    return 6 * K + 10 * sum(ranks)
+
+
+def cpu_baseline(cfg, p, U, G, V, sample, seed):
+    import oracle
+    from synth import item_order
+    params = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices])
+    order = item_order(p.n_items, seed, 0)[:sample]
+    t = time.perf_counter()
+    oracle.sgd_epoch(params, p, order, cfg.eta0)
+    dt = time.perf_counter() - t
+    return {"value": sample / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"sequential FP64 SGD (Algorithm 1, one worker) over the first {sample:,} items of an "
+                      f"epoch order of the same workload ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed epochs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed epochs before the timed ones")
+    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--mode", default="lockfree", choices=["lockfree", "det"])
+    ap.add_argument("--round-items", type=int, default=65536)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=7)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1708_08640_amd import S3Plan
+    from synth import get_config, init_params, item_order, make_problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = get_config(args.config)
+    log(f"generating {cfg.name}: {cfg.description}")
+    p = make_problem(cfg)
+    U, G, V = init_params(cfg)
+    n_updates = p.n_items
+    log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {n_updates - p.n_train:,} matrix entries")
+    order = item_order(p.n_items, args.seed, 0) if args.mode == "det" else None
+    plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", batch=args.batch, order=order, damping=True,
+                               round_items=args.round_items, seed=args.seed)
+    torch.cuda.synchronize()
+    rmse0 = plan.rmse()
+    log(f"bound; initial held-out RMSE {rmse0:.4f}")
+
+    for e in range(args.warmup):
+        plan.epoch(e, args.mode)
+        torch.cuda.synchronize()
+        log(f"warmup epoch {e}: RMSE {plan.rmse():.4f}")
+
+    plan.set_profiling(True)
+    kernel_ms, launches, epoch_ms = 0.0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(args.warmup, args.warmup + args.steps):
+        te = time.perf_counter()
+        plan.epoch(e, args.mode)
+        ms, n = plan.last_epoch_profile()  # waits for the epoch
+        kernel_ms += ms
+        launches += n
+        epoch_ms.append((time.perf_counter() - te) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_profiling(False)
+    rmse = plan.rmse()
+    E = args.warmup + args.steps
+    log(f"timed {args.steps} epochs: {(t1 - t0) * 1e3 / args.steps:.3f} ms/epoch; RMSE after {E} epochs {rmse:.4f}")
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n_updates / (ms_per_step / 1e3)
+
+    # held-out RMSE target from the oracle's trajectory (sequential FP64 SGD)
+    target = None
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle_rmse.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        if len(g["rmse"]) >= E:
+            target = 1.01 * g["rmse"][E - 1]
+
+    flops = tensor_entry_flops(cfg.ranks) * p.n_train * args.steps
+    achieved = flops / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else None
+    roofline = {
+        "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_tensor",
+        "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+        "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None, "traffic": None,
+        "flops_per_entry": tensor_entry_flops(cfg.ranks), "launches": launches,
+        "avg_launch_ms": kernel_ms / max(launches, 1), "kernel_share_of_epoch": kernel_ms / (t1 - t0) / 1e3,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"timing the FP64 oracle on {args.cpu_sample:,} items (CPU baseline)")
+        cpu = cpu_baseline(cfg, p, U, G, V, args.cpu_sample, args.seed)
+        log(f"oracle: {cpu['value']:.0f} updates/s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.description}", "mode": args.mode,
+                   "round_items": args.round_items if args.mode == "lockfree" else None,
+                   "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
+                   "updates_per_epoch": n_updates, "parallelism": "single GPU"},
+        "heldout_rmse": rmse, "heldout_rmse_init": rmse0, "rmse_epochs": E, "rmse_target": target,
+        "rmse_ok": (rmse <= target) if target is not None else None,
+        "epoch_ms": epoch_ms,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

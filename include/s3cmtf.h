@@ -213,9 +213,15 @@ s3_status s3_export(s3_plan *plan, int32_t which, int32_t index, double *host_ds
  * (round-to-nearest-even).  Call after filling the masters.  Asynchronous. */
 s3_status s3_sync_bf16(s3_plan *plan, void *stream);
 
-/* Duration in milliseconds of the dominant kernel's launches during the
- * last s3_epoch (measured with HIP events on the plan's stream), and the
- * number of those launches; for bandwidth/flop accounting.               */
+/* Turn per-launch timing of the dominant kernel (the tensor-entry kernel of
+ * the epoch's mode) on or off; off by default.  When on, s3_epoch records a
+ * pair of HIP events around each such launch on the epoch's stream.        */
+s3_status s3_set_profiling(s3_plan *plan, int32_t on);
+
+/* After s3_epoch: with profiling on, the summed duration in milliseconds of
+ * the dominant kernel's launches and their count; with profiling off, the
+ * whole epoch's duration and the number of batches / rounds.  Waits for the
+ * epoch to finish.                                                          */
 s3_status s3_last_epoch_profile(const s3_plan *plan, double *kernel_ms, int64_t *launches);
 
 #ifdef __cplusplus

@@ -17,6 +17,7 @@
 
 namespace s3 {
 
+
 template <int JP, typename T, typename GP>
 S3_DEV void contract3(GP G, const T (&a)[JP], const T (&b)[JP], const T (&c)[JP],
                       T (&w1)[JP], T (&w2)[JP], T (&w3)[JP], T &xhat) {
@@ -61,7 +62,7 @@ S3_DEV void contract4(GP G, const T (&a)[JP], const T (&b)[JP], const T (&c)[JP]
             T s2 = T(0);
 #pragma unroll
             for (int j3 = 0; j3 < JP; ++j3) {
-                const T abc = ab * c[j3];
+                    const T abc = ab * c[j3];
                 T t = T(0);
 #pragma unroll
                 for (int j4 = 0; j4 < JP; ++j4) {

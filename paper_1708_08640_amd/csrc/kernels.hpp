@@ -219,45 +219,50 @@ S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t 
 // ------------------------------------------------------------ det: entries
 
 // One lane per tensor entry of the batch.  Scratch row layout per entry:
-//   [ g_1 (J_1) | ... | g_N (J_N) | L_1 .. L_N | q | L_G ]
+//   [ g_1 (JP) | ... | g_N (JP) | L_1 .. L_N | q | L_G ]   (stride N*JP + N + 2)
 // where g_n = q w_n + (lambda_reg / cnt_n) u_n is the Eq (8) row gradient,
 // q = -e (training) or the upstream sensitivity (adjoint), L_n = |w_n|^2 +
 // lambda_reg / cnt_n and L_G = prod_n |u_n|^2 the curvatures.
-template <int N, int JP, typename T>
+// ADJ = false: training gradients; ADJ = true: adjoint (q = gx[e], no
+// regulariser).  The mode is a template flag and the entry's value is loaded
+// before the contraction: with a run-time choice between two loads after it
+// the compiler front-loads every scalar core load and spills them.
+template <int N, int JP, typename T, bool ADJ>
 __global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32_t *__restrict__ ids,
                                                     int64_t nt, const T *__restrict__ Gp,
                                                     T *__restrict__ scr, int64_t stride,
                                                     const T *__restrict__ gx) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nt) return;
-    const int64_t e = ids[s];
-    T u[N][JP], w[N][JP];
-    int32_t rows[N];
-    load_rows<N, JP, T>(A, e, u, rows);
-    T xhat;
-    contract<N, JP, T>(Gp, u, w, xhat);
-    const bool train = (gx == nullptr);
-    const T q = train ? -(A.val[e] - xhat) : gx[e];
-    T *out = scr + s * stride;
-    const int64_t cbase = stride - N - 2;  // curvature slots
-    int off = 0;
-    T LG = T(1);
+    if (s < nt) {
+        const int64_t e = ids[s];
+        T u[N][JP], w[N][JP];
+        int32_t rows[N];
+        load_rows<N, JP, T>(A, e, u, rows);
+        const T xv = ADJ ? gx[e] : A.val[e];
+        T xhat;
+        contract<N, JP, T>(Gp, u, w, xhat);
+        constexpr bool train = !ADJ;
+        const T q = train ? -(xv - xhat) : xv;
+        // fixed JP stride per mode (padding lanes hold zeros): stores at
+        // run-time offsets here also make the compiler spill the core loads
+        T *out = scr + s * stride;
+        T LG = T(1);
 #pragma unroll
-    for (int n = 0; n < N; ++n) {
-        const T reg = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
-        T ww = T(0), uu = T(0);
+        for (int n = 0; n < N; ++n) {
+            const T reg = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
+            T ww = T(0), uu = T(0);
 #pragma unroll
-        for (int k = 0; k < JP; ++k) {
-            if (k < A.J[n]) out[off + k] = fmaT(q, w[n][k], reg * u[n][k]);
-            ww = fmaT(w[n][k], w[n][k], ww);
-            uu = fmaT(u[n][k], u[n][k], uu);
+            for (int k = 0; k < JP; ++k) {
+                out[n * JP + k] = fmaT(q, w[n][k], reg * u[n][k]);
+                ww = fmaT(w[n][k], w[n][k], ww);
+                uu = fmaT(u[n][k], u[n][k], uu);
+            }
+            out[N * JP + n] = ww + reg;
+            LG *= uu;
         }
-        off += A.J[n];
-        out[cbase + n] = ww + reg;
-        LG *= uu;
+        out[stride - 2] = q;
+        out[stride - 1] = LG;
     }
-    out[stride - 2] = q;
-    out[stride - 1] = LG;
 }
 
 // One lane per coupled-matrix entry.  Scratch row: [ g_u (J) | g_v (J) | L_u | L_v ].
@@ -456,19 +461,20 @@ __global__ __launch_bounds__(256) void k_rows_apply(const uint64_t *__restrict__
 
 // ---------------------------------------------------------------- evaluation
 
-// sum over entries of (x - x~)^2 into per-block double partials (fixed order)
+// sum over entries of (x - x~)^2: one entry per thread, one double partial
+// per block (the host adds the partials in block order: deterministic)
 template <int N, int JP, typename T>
 __global__ __launch_bounds__(256) void k_sq_err_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
                                                        double *__restrict__ part) {
     __shared__ double s[256];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < A.nnz) {
         T u[N][JP];
         int32_t rows[N];
         load_rows<N, JP, T>(A, e, u, rows);
         const T r = A.val[e] - predict<N, JP, T>(Gp, u);
-        acc += (double)r * (double)r;
+        acc = (double)r * (double)r;
     }
     s[threadIdx.x] = acc;
     __syncthreads();
@@ -482,8 +488,8 @@ __global__ __launch_bounds__(256) void k_sq_err_tensor(TensorArgs<T> A, const T 
 template <int N, int JP, typename T>
 __global__ __launch_bounds__(256) void k_predict(TensorArgs<T> A, const T *__restrict__ Gp,
                                                  T *__restrict__ out) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < A.nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < A.nnz) {
         T u[N][JP];
         int32_t rows[N];
         load_rows<N, JP, T>(A, e, u, rows);

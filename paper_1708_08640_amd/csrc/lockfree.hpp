@@ -3,18 +3,25 @@
 //
 // An epoch is a sequence of rounds; a round takes a slice of 256-entry
 // tiles (tensor and coupled-matrix tiles, in a per-epoch shuffled tile
-// order) and runs three launches:
-//   k_lf_tensor / k_lf_matrix  one lane per entry, reads the current
-//          factor rows without locks; the row it moves:
-//            cold row -> at once, atomic add of -eta g / max(1, k eta L)
-//                        (HOGWILD!-style; a row touched by one entry of the
-//                        round moves exactly like one SGD step)
-//            hot row  -> gradient and curvature summed in an LDS table per
-//                        workgroup, flushed to a global accumulator
-//          and the core gradient is summed per workgroup (LDS staging)
-//          into a global accumulator.
-//   k_lf_apply  moves every hot row and the core once by the damped step
-//          -eta sum g / max(1, k eta sum L) and clears the accumulators.
+// order) and runs:
+//   k_lf_tensor / k_lf_matrix  one workgroup per tile, one lane per entry;
+//          each lane reads the current factor rows without locks, and for
+//          each row it moves:
+//            cold row -> at once, u <- u - eta g / max(1, k eta L) written
+//                        back with plain stores (HOGWILD!-style: no lock, a
+//                        concurrent write to the same row may win; a row
+//                        touched by one entry of the round moves exactly like
+//                        one SGD step)
+//            hot row  -> gradient and curvature summed in an LDS table of
+//                        the workgroup
+//          the tile's core gradient is summed in registers (LDS-staged
+//          operands); at the end the workgroup writes its whole hot-row
+//          table and core partial to its own slot of a partials buffer
+//          (plain coalesced stores: no global atomics).
+//   k_lf_apply  one workgroup per hot row (and per core chunk): sums the
+//          partials of every workgroup of the round in a fixed order and
+//          moves the row / the core once by the damped step
+//          -eta sum g / max(1, k eta sum L).
 // "Hot" rows are the H most frequent rows of each mode and of each coupled
 // factor.  The paper lets one worker own the core, which every entry
 // touches; power-law data (a handful of rows in 10-30 % of all entries)
@@ -35,18 +42,26 @@ constexpr int kTile = 256;
 
 template <typename T> struct LFArgs {
     const int32_t *hot_slot[kMaxN + kMaxM];  // row -> slot in [0, H) or -1
-    T *acc;                                  // [(N + M)][H][JP + 1]
-    T *accG;                                 // [KP] then [KP] = curvature, [KP+1] = entry count
+    T *tab_out;        // per-workgroup hot tables: [wg][groups][H][JP + 1]
+    T *core_out;       // per-workgroup core partials: [wg][KP + 2] (tensor only)
     int H;
     int JP;
     int64_t n_tiles;   // tiles of this kind
     int64_t tile_base; // first (permuted) tile index of this round
-    int64_t n_round;   // tiles in this round
     uint64_t pa, pb;   // tile permutation i -> (pa * i + pb) mod n_tiles
 };
 
 S3_DEV int64_t lf_perm(int64_t i, uint64_t pa, uint64_t pb, int64_t n) {
     return (int64_t)((pa * (uint64_t)i + pb) % (uint64_t)n);  // pa, i < 2^31
+}
+
+// mode-1 slices per core-gradient work item: enough items for a 256-thread
+// tile when the tail is short, and a divisor of JP
+template <int JP, int TAIL> constexpr int lf_split() {
+    int best = 1;
+    for (int s = 1; s <= JP; ++s)
+        if (JP % s == 0 && TAIL * s <= kTile) best = s;
+    return best;
 }
 
 // ------------------------------------------------------------------ tensor
@@ -55,7 +70,7 @@ template <int N, int JP, typename T>
 __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *__restrict__ Gp, LFArgs<T> L,
                                                      T eta, T kappa) {
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
-    constexpr int SUB = 64;
+    constexpr int KP = JP * TAIL;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *s_tab = (T *)smem_raw;                         // [N][H][JP + 1]
     T *s_q = s_tab + (size_t)N * L.H * (JP + 1);     // [kTile][JP]  q * u^(1)
@@ -69,14 +84,14 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
 
     const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
     const int64_t e = tile * kTile + tid;
-    const bool live = e < A.nnz;
-    T u[N][JP], w[N][JP];
-    int32_t rows[N];
-    if (live) {
+    if (e < A.nnz) {
+        T u[N][JP], w[N][JP];
+        int32_t rows[N];
         load_rows<N, JP, T>(A, e, u, rows);
+        const T xv = A.val[e];
         T xhat;
         contract<N, JP, T>(Gp, u, w, xhat);
-        const T q = -(A.val[e] - xhat);
+        const T q = -(xv - xhat);
         T LG = T(1);
 #pragma unroll
         for (int n = 0; n < N; ++n) {
@@ -93,8 +108,7 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
             if (slot >= 0) {
                 T *t = s_tab + ((size_t)n * L.H + slot) * (JP + 1);
 #pragma unroll
-                for (int k = 0; k < JP; ++k)
-                    if (k < A.J[n]) atomicAdd(&t[k], fmaT(q, w[n][k], reg * u[n][k]));
+                for (int k = 0; k < JP; ++k) atomicAdd(&t[k], fmaT(q, w[n][k], reg * u[n][k]));
                 atomicAdd(&t[JP], ell);
             } else {
                 const T d = kappa * eta * ell;
@@ -102,7 +116,7 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
                 T *r = A.U[n] + (int64_t)rows[n] * A.J[n];
 #pragma unroll
                 for (int k = 0; k < JP; ++k)
-                    if (k < A.J[n]) atomicAdd(&r[k], -step * fmaT(q, w[n][k], reg * u[n][k]));
+                    if (k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
             }
         }
         // stage the core-gradient operands
@@ -123,40 +137,37 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
             for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = T(0);
     }
     __syncthreads();
-    // core gradient of this tile: thread owns tail indices tau (modes 2..N)
-    for (int tau = tid; tau < TAIL; tau += kTile) {
+    // core gradient of this tile: work item = (tail index tau over modes
+    // 2..N, slice of JS consecutive mode-1 indices); all threads take part
+    constexpr int SPLIT = lf_split<JP, TAIL>();
+    constexpr int JS = JP / SPLIT;
+    T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
+    for (int item = tid; item < TAIL * SPLIT; item += kTile) {
+        const int tau = item % TAIL, j0 = (item / TAIL) * JS;
         int tj[N - 1];
         int r = tau;
 #pragma unroll
         for (int n = N - 2; n >= 0; --n) { tj[n] = r % JP; r /= JP; }
-        T acc[JP];
+        T acc[JS];
 #pragma unroll
-        for (int k = 0; k < JP; ++k) acc[k] = T(0);
-        for (int t0 = 0; t0 < kTile; t0 += SUB) {
-            for (int t = t0; t < t0 + SUB; ++t) {
-                T p = s_u[((size_t)t * (N - 1)) * JP + tj[0]];
+        for (int k = 0; k < JS; ++k) acc[k] = T(0);
+        for (int t = 0; t < kTile; ++t) {
+            T p = s_u[((size_t)t * (N - 1)) * JP + tj[0]];
 #pragma unroll
-                for (int n = 1; n < N - 1; ++n) p *= s_u[((size_t)t * (N - 1) + n) * JP + tj[n]];
+            for (int n = 1; n < N - 1; ++n) p *= s_u[((size_t)t * (N - 1) + n) * JP + tj[n]];
 #pragma unroll
-                for (int k = 0; k < JP; ++k) acc[k] = fmaT(s_q[t * JP + k], p, acc[k]);
-            }
+            for (int k = 0; k < JS; ++k) acc[k] = fmaT(s_q[t * JP + j0 + k], p, acc[k]);
         }
 #pragma unroll
-        for (int k = 0; k < JP; ++k) atomicAdd(&L.accG[(size_t)k * TAIL + tau], acc[k]);
+        for (int k = 0; k < JS; ++k) core[(size_t)(j0 + k) * TAIL + tau] = acc[k];
     }
     if (tid == 0) {
-        const int64_t KP = (int64_t)JP * TAIL;
-        atomicAdd(&L.accG[KP], s_misc[0]);
-        atomicAdd(&L.accG[KP + 1], s_misc[1]);
+        core[KP] = s_misc[0];
+        core[KP + 1] = s_misc[1];
     }
-    // flush touched hot rows
-    for (int i = tid; i < N * L.H; i += kTile) {
-        const T *t = s_tab + (size_t)i * (JP + 1);
-        if (t[JP] != T(0)) {
-            T *g = L.acc + (size_t)i * (JP + 1);
-            for (int k = 0; k <= JP; ++k) atomicAdd(&g[k], t[k]);
-        }
-    }
+    // the workgroup's hot-row table, written densely
+    T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
+    for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
 }
 
 // ------------------------------------------------------------------ matrix
@@ -171,7 +182,8 @@ __global__ __launch_bounds__(kTile) void k_lf_matrix(const int32_t *__restrict__
     T *s_tab = (T *)smem_raw;  // [2][H][JP + 1]: coupled-mode rows, then V rows
     const int JP = L.JP;
     const int tid = threadIdx.x;
-    for (int i = tid; i < 2 * L.H * (JP + 1); i += kTile) s_tab[i] = T(0);
+    const int tabn = 2 * L.H * (JP + 1);
+    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
     __syncthreads();
     const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
     const int64_t e = tile * kTile + tid;
@@ -199,7 +211,7 @@ __global__ __launch_bounds__(kTile) void k_lf_matrix(const int32_t *__restrict__
         } else {
             const T d = kappa * eta * Lu;
             const T step = eta / (d > T(1) ? d : T(1));
-            for (int k = 0; k < J; ++k) atomicAdd(&u[k], -step * q * vr[k]);
+            for (int k = 0; k < J; ++k) u[k] = ur[k] - step * q * vr[k];
         }
         if (sv >= 0) {
             T *t = s_tab + ((size_t)L.H + sv) * (JP + 1);
@@ -208,76 +220,122 @@ __global__ __launch_bounds__(kTile) void k_lf_matrix(const int32_t *__restrict__
         } else {
             const T d = kappa * eta * Lv;
             const T step = eta / (d > T(1) ? d : T(1));
-            for (int k = 0; k < J; ++k) atomicAdd(&v[k], -step * fmaT(q, ur[k], rv * vr[k]));
+            for (int k = 0; k < J; ++k) v[k] = vr[k] - step * fmaT(q, ur[k], rv * vr[k]);
         }
     }
     __syncthreads();
-    for (int i = tid; i < 2 * L.H; i += kTile) {
-        const T *t = s_tab + (size_t)i * (JP + 1);
-        if (t[JP] != T(0)) {
-            const int g = (i < L.H) ? gu : gv;
-            const int slot = (i < L.H) ? i : i - L.H;
-            T *dst = L.acc + ((size_t)g * L.H + slot) * (JP + 1);
-            for (int k = 0; k <= JP; ++k) atomicAdd(&dst[k], t[k]);
-        }
-    }
+    T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
+    for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
 }
 
 // ------------------------------------------------------------------- apply
 
+// Sources of one hot-row group in the round's partials: the tensor tables
+// (group g < N) and every matrix table whose u-side (c_m == g) or V-side
+// (g == N + m) is that group.
 struct LFApplyArgs {
-    void *P[kMaxN + kMaxM];        // parameter of each group
+    void *P[kMaxN + kMaxM];                 // parameter of each group
     const int32_t *hot_row[kMaxN + kMaxM];  // slot -> row (or -1)
     int J[kMaxN + kMaxM];
     int groups;
+    int N, M;
+    int mat_mode[kMaxM];
+    const void *tab_t;                      // tensor tables [nwg_t][N][H][JP+1]
+    int64_t nwg_t;
+    const void *tab_m[kMaxM];               // matrix tables [nwg_m][2][H][JP+1]
+    int64_t nwg_m[kMaxM];
+    const void *core_t;                     // tensor core partials [nwg_t][KP+2]
 };
 
+constexpr int kApplyThreads = 256;
+
+// fixed-order tree sum over the block of n values per thread (n <= 17)
+template <typename T> S3_DEV void lf_block_sum(T *vals, int n, T *s_red) {
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n; ++k) s_red[k * kApplyThreads + tid] = vals[k];
+    __syncthreads();
+    for (int w = kApplyThreads / 2; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int k = 0; k < n; ++k) s_red[k * kApplyThreads + tid] += s_red[k * kApplyThreads + tid + w];
+        __syncthreads();
+    }
+    for (int k = 0; k < n; ++k) vals[k] = s_red[k * kApplyThreads];
+}
+
+// blocks [0, groups * H): one hot row each; blocks after: core chunks of
+// kApplyThreads elements
 template <int N, typename T>
-__global__ void k_lf_apply(LFApplyArgs a, T *__restrict__ acc, int H, int JP, T *__restrict__ G,
-                           T *__restrict__ Gp, T *__restrict__ accG, int J0, int J1, int J2, int J3,
-                           T reg_core, T eta, T kappa) {
-    const int Js[4] = {J0, J1, J2, J3};
-    int K = 1, KP = 1;
-    for (int n = 0; n < N; ++n) { K *= Js[n]; KP *= JP; }
-    const int nrow = a.groups * H;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < nrow) {
-        const int g = (int)(tid / H), slot = (int)(tid % H);
-        T *t = acc + (size_t)tid * (JP + 1);
+__global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H, int JP, T *__restrict__ G,
+                                                            T *__restrict__ Gp, int J0, int J1, int J2, int J3,
+                                                            T reg_core, T eta, T kappa) {
+    __shared__ T s_red[17 * kApplyThreads];
+    const int tid = threadIdx.x;
+    const int nrowblk = a.groups * H;
+    if ((int)blockIdx.x < nrowblk) {
+        const int g = blockIdx.x / H, slot = blockIdx.x % H;
         const int row = a.hot_row[g][slot];
-        const T Lsum = t[JP];
-        if (row >= 0 && Lsum != T(0)) {
+        if (row < 0) return;  // uniform over the block
+        T acc[17];
+        for (int k = 0; k < 17; ++k) acc[k] = T(0);
+        const size_t W = (size_t)JP + 1;
+        if (g < N) {
+            const T *src = (const T *)a.tab_t + ((size_t)g * H + slot) * W;
+            const size_t stride = (size_t)N * H * W;
+            for (int64_t b = tid; b < a.nwg_t; b += kApplyThreads)
+                for (int k = 0; k <= JP; ++k) acc[k] += src[b * stride + k];
+        }
+        for (int m = 0; m < a.M; ++m) {
+            int side = -1;
+            if (g < N && a.mat_mode[m] == g) side = 0;
+            if (g == N + m) side = 1;
+            if (side < 0) continue;
+            const T *src = (const T *)a.tab_m[m] + ((size_t)side * H + slot) * W;
+            const size_t stride = (size_t)2 * H * W;
+            for (int64_t b = tid; b < a.nwg_m[m]; b += kApplyThreads)
+                for (int k = 0; k <= JP; ++k) acc[k] += src[b * stride + k];
+        }
+        lf_block_sum<T>(acc, JP + 1, s_red);
+        const T Lsum = acc[JP];
+        if (Lsum != T(0) && tid < a.J[g]) {
             const T d = kappa * eta * Lsum;
             const T step = eta / (d > T(1) ? d : T(1));
             T *p = (T *)a.P[g] + (int64_t)row * a.J[g];
-            for (int k = 0; k < a.J[g]; ++k) p[k] -= step * t[k];
+            T gk = T(0);
+            for (int k = 0; k < JP; ++k)
+                if (k == tid) gk = acc[k];
+            p[tid] -= step * gk;
         }
-        for (int k = 0; k <= JP; ++k) t[k] = T(0);
-    } else if (tid < nrow + K) {
-        const int j = (int)(tid - nrow);
-        int rem = j, pj = 0, mul = 1;
-        for (int n = N - 1; n >= 0; --n) {
-            const int jn = rem % Js[n];
-            rem /= Js[n];
-            pj += jn * mul;
-            mul *= JP;
-        }
-        const T cntT = accG[KP + 1];
-        if (cntT != T(0)) {
-            const T Lsum = accG[KP] + cntT * reg_core;
-            const T d = kappa * eta * Lsum;
-            const T step = eta / (d > T(1) ? d : T(1));
-            const T gnew = G[j] - step * (accG[pj] + cntT * reg_core * G[j]);
-            G[j] = gnew;
-            Gp[pj] = gnew;
-        }
+        return;
     }
-}
-
-// clear the core accumulator (after every thread of k_lf_apply has read it)
-template <typename T> __global__ void k_lf_clear(T *__restrict__ accG, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        accG[i] = T(0);
+    // core
+    const int Js[4] = {J0, J1, J2, J3};
+    int K = 1, KP = 1;
+    for (int n = 0; n < N; ++n) { K *= Js[n]; KP *= JP; }
+    const int j = (blockIdx.x - nrowblk) * kApplyThreads + tid;
+    const T *core = (const T *)a.core_t;
+    const size_t cs = (size_t)KP + 2;
+    // every thread needs the round's total core curvature and entry count
+    T LG = T(0), cnt = T(0);
+    for (int64_t b = 0; b < a.nwg_t; ++b) {
+        LG += core[b * cs + KP];
+        cnt += core[b * cs + KP + 1];
+    }
+    if (j >= K || cnt == T(0)) return;
+    int rem = j, pj = 0, mul = 1;
+    for (int n = N - 1; n >= 0; --n) {
+        const int jn = rem % Js[n];
+        rem /= Js[n];
+        pj += jn * mul;
+        mul *= JP;
+    }
+    T s = T(0);
+    for (int64_t b = 0; b < a.nwg_t; ++b) s += core[b * cs + pj];
+    const T Lsum = LG + cnt * reg_core;
+    const T d = kappa * eta * Lsum;
+    const T step = eta / (d > T(1) ? d : T(1));
+    const T gnew = G[j] - step * (s + cnt * reg_core * G[j]);
+    G[j] = gnew;
+    Gp[pj] = gnew;
 }
 
 // ------------------------------------------------------------------- state
@@ -288,22 +346,19 @@ struct LockFreeState {
     int64_t nX = 0, y_nnz[kMaxM] = {};
     int64_t n_items = 0, n_rounds = 0;
     int64_t t_tiles = 0, m_tiles[kMaxM] = {};
+    int64_t max_t_wg = 0, max_m_wg[kMaxM] = {};
     int32_t *hot_slot[kMaxN + kMaxM] = {};
     int32_t *hot_row[kMaxN + kMaxM] = {};
     int64_t rows[kMaxN + kMaxM] = {};
-    void *acc = nullptr;
-    void *accG = nullptr;
+    void *tab_t = nullptr, *core_t = nullptr;
+    void *tab_m[kMaxM] = {};
     uint64_t seed = 0;
     bool ready = false;
     // per-launch state for the tensor kernel (set by lockfree_epoch)
     uint64_t pa = 1, pb = 0;
-    int64_t tile_base = 0, n_round = 0;
     LFApplyArgs apply{};
-    int J[kMaxN] = {};
-    double lambda_reg = 0, lambda_m = 0;
-    const s3_buffers *buf = nullptr;
-    s3_buffers b{};
     const int32_t *cntV[kMaxM] = {};
+    s3_buffers b{};
 };
 
 constexpr size_t kLfLdsBudget = 64 * 1024;
@@ -324,20 +379,27 @@ void lockfree_layout(LockFreeState &s, C &c, int N, int M, const s3_desc &d, int
     s.JP = JP;
     s.KP = KP;
     s.H = lf_hot_rows(N, JP, sizeof(T));
+    const int H = std::max(s.H, 1);
+    int64_t n_items = x_nnz;
+    for (int m = 0; m < M; ++m) n_items += y_nnz[m];
+    const int64_t R = std::max<int64_t>(1, (n_items + d.round_items - 1) / d.round_items);
+    const int64_t tt = (x_nnz + kTile - 1) / kTile;
+    s.max_t_wg = (tt + R - 1) / R + 1;
     for (int n = 0; n < N; ++n) {
         s.rows[n] = d.dims[n];
         s.hot_slot[n] = c.template take<int32_t>((size_t)d.dims[n]);
-        s.hot_row[n] = c.template take<int32_t>((size_t)s.H);
+        s.hot_row[n] = c.template take<int32_t>((size_t)H);
     }
     for (int m = 0; m < M; ++m) {
         s.rows[N + m] = d.mat_cols[m];
         s.hot_slot[N + m] = c.template take<int32_t>((size_t)d.mat_cols[m]);
-        s.hot_row[N + m] = c.template take<int32_t>((size_t)s.H);
+        s.hot_row[N + m] = c.template take<int32_t>((size_t)H);
+        const int64_t mt = (y_nnz[m] + kTile - 1) / kTile;
+        s.max_m_wg[m] = (mt + R - 1) / R + 1;
+        s.tab_m[m] = c.template take<T>((size_t)s.max_m_wg[m] * 2 * H * (JP + 1));
     }
-    s.acc = c.template take<T>((size_t)(N + M) * s.H * (JP + 1));
-    s.accG = c.template take<T>((size_t)KP + 2);
-    (void)x_nnz;
-    (void)y_nnz;
+    s.tab_t = c.template take<T>((size_t)s.max_t_wg * N * H * (JP + 1));
+    s.core_t = c.template take<T>((size_t)s.max_t_wg * (KP + 2));
 }
 
 // pick the H most frequent rows of every group (host side, from the counts)
@@ -348,18 +410,16 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
     s.nX = nX;
     s.n_items = nX;
     s.b = *buf;
-    s.lambda_reg = d.lambda_reg;
-    s.lambda_m = d.lambda_m;
     for (int m = 0; m < M; ++m) {
         s.y_nnz[m] = y_nnz[m];
         s.n_items += y_nnz[m];
         s.cntV[m] = cntV[m];
     }
-    for (int n = 0; n < N; ++n) s.J[n] = d.rank[n];
     s.seed = d.seed;
     s.n_rounds = std::max<int64_t>(1, (s.n_items + d.round_items - 1) / d.round_items);
     s.t_tiles = (nX + kTile - 1) / kTile;
     for (int m = 0; m < M; ++m) s.m_tiles[m] = (y_nnz[m] + kTile - 1) / kTile;
+    if (s.H == 0) return S3_OK;  // lock-free mode unavailable; reported by s3_epoch
     for (int g = 0; g < N + M; ++g) {
         const int64_t R = s.rows[g];
         std::vector<int32_t> h((size_t)R);
@@ -392,23 +452,27 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
         s.apply.J[g] = (g < N) ? d.rank[g] : d.rank[d.mat_mode[g - N]];
     }
     s.apply.groups = N + M;
-    const int64_t nacc = (int64_t)(N + M) * s.H * (s.JP + 1);
-    hipLaunchKernelGGL(k_fill<T>, dim3(64), dim3(256), 0, st, (T *)s.acc, nacc, T(0));
-    hipLaunchKernelGGL(k_fill<T>, dim3(64), dim3(256), 0, st, (T *)s.accG, s.KP + 2, T(0));
+    s.apply.N = N;
+    s.apply.M = M;
+    for (int m = 0; m < M; ++m) {
+        s.apply.mat_mode[m] = d.mat_mode[m];
+        s.apply.tab_m[m] = s.tab_m[m];
+    }
+    s.apply.tab_t = s.tab_t;
+    s.apply.core_t = s.core_t;
     s.ready = true;
     return S3_OK;
 }
 
-template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles, int64_t base, int64_t count) {
+template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles, int64_t base, T *tab, T *core) {
     LFArgs<T> L{};
     for (int g = 0; g < s.N + s.M; ++g) L.hot_slot[g] = s.hot_slot[g];
-    L.acc = (T *)s.acc;
-    L.accG = (T *)s.accG;
+    L.tab_out = tab;
+    L.core_out = core;
     L.H = s.H;
     L.JP = s.JP;
     L.n_tiles = n_tiles;
     L.tile_base = base;
-    L.n_round = count;
     L.pa = s.pa;
     L.pb = s.pb;
     return L;
@@ -418,7 +482,7 @@ template <int N, int JP, typename T>
 void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
                             T eta, hipStream_t st) {
     if (count <= 0) return;
-    LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, count);
+    LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
     const size_t smem = ((size_t)N * s.H * (JP + 1) + (size_t)kTile * JP * N + 2) * sizeof(T);
     hipLaunchKernelGGL((k_lf_tensor<N, JP, T>), dim3((unsigned)count), dim3(kTile), smem, st, A, Gp, L, eta,
                        (T)(N + 1));
@@ -441,7 +505,7 @@ inline void pick_perm(uint64_t &rng, int64_t n, uint64_t &pa, uint64_t &pb) {
 }
 
 // One lock-free epoch.  tensor_round(first_tile, count, eta, stream) launches
-// the tensor kernel for one round (the caller owns the core padding).
+// the tensor kernel for one round; the caller padded the core into Gp.
 template <typename T, typename F>
 s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double eta, T *Gp, hipStream_t st,
                          std::string &err, F tensor_round) {
@@ -455,7 +519,6 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
     const T kappa = (T)(N + 1);
     const T reg_core = (T)(d.lambda_reg / (double)s.nX);
     const int *J = d.rank;
-    const int64_t nrow = (int64_t)(N + M) * s.H;
     int64_t K = 1;
     for (int n = 0; n < N; ++n) K *= J[n];
     for (int64_t r = 0; r < R; ++r) {
@@ -463,24 +526,24 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
         s.pa = tpa;
         s.pb = tpb;
         tensor_round(t0, t1 - t0, eta, st);
+        s.apply.nwg_t = t1 - t0;
         for (int m = 0; m < M; ++m) {
             const int64_t m0 = s.m_tiles[m] * r / R, m1 = s.m_tiles[m] * (r + 1) / R;
+            s.apply.nwg_m[m] = std::max<int64_t>(0, m1 - m0);
             if (m1 <= m0) continue;
             s.pa = mpa[m];
             s.pb = mpb[m];
-            LFArgs<T> L = lf_args<T>(s, s.m_tiles[m], m0, m1 - m0);
+            LFArgs<T> L = lf_args<T>(s, s.m_tiles[m], m0, (T *)s.tab_m[m], nullptr);
             const int c = d.mat_mode[m];
             const size_t smem = (size_t)2 * s.H * (s.JP + 1) * sizeof(T);
             hipLaunchKernelGGL(k_lf_matrix<T>, dim3((unsigned)(m1 - m0)), dim3(kTile), smem, st, s.b.y_row[m],
                                s.b.y_col[m], (const T *)s.b.y_val[m], s.y_nnz[m], (T *)s.b.U[c], (T *)s.b.V[m],
                                J[c], s.cntV[m], (T)d.lambda_m, (T)d.lambda_reg, L, c, N + m, (T)eta, kappa);
         }
-        const int64_t nthreads = nrow + K;
+        const int64_t blocks = (int64_t)(N + M) * s.H + (K + kApplyThreads - 1) / kApplyThreads;
         auto kern = (N == 3) ? k_lf_apply<3, T> : k_lf_apply<4, T>;
-        hipLaunchKernelGGL(kern, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, s.apply, (T *)s.acc,
-                           s.H, s.JP, (T *)s.b.G, Gp, (T *)s.accG, J[0], J[1], J[2],
-                           N > 3 ? J[3] : 1, reg_core, (T)eta, kappa);
-        hipLaunchKernelGGL(k_lf_clear<T>, dim3(16), dim3(256), 0, st, (T *)s.accG, s.KP + 2);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kApplyThreads), 0, st, s.apply, s.H, s.JP,
+                           (T *)s.b.G, Gp, J[0], J[1], J[2], N > 3 ? J[3] : 1, reg_core, (T)eta, kappa);
     }
     return S3_OK;
 }

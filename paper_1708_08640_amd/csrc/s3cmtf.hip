@@ -74,6 +74,7 @@ struct s3_plan {
     void *Gp = nullptr;
     int32_t *flag = nullptr;
     double *red = nullptr;  // reduction partials
+    int64_t n_red = 0;
     std::vector<double> h_red;
     // det structures
     int64_t nX = 0, nT = 0, n_items = 0, n_batches = 0;
@@ -94,6 +95,9 @@ struct s3_plan {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
     int64_t last_launches = 0;
+    bool prof = false;
+    std::vector<hipEvent_t> pev;  // pairs around the dominant kernel
+    size_t pev_used = 0;
 };
 
 namespace {
@@ -116,6 +120,9 @@ s3_status fail(s3_plan *p, s3_status st, const char *fmt, ...) {
         if (e_ != hipSuccess)                                                                   \
             return fail(plan, S3_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
+
+// blocks of the one-entry-per-thread squared-error kernel
+inline int64_t sq_blocks(int64_t nnz) { return std::max<int64_t>(1, (nnz + 255) / 256); }
 
 inline int grid_for(int64_t n, int tpb, int64_t cap = 65535 * 4) {
     int64_t g = (n + tpb - 1) / tpb;
@@ -142,8 +149,12 @@ template <typename T> TensorArgs<T> tensor_args(const s3_plan *p, const int32_t 
 template <int N, int JP, typename T> struct Impl {
     static void det_tensor(s3_plan *p, const int32_t *ids, int64_t nt, const void *gx, hipStream_t st) {
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
-        hipLaunchKernelGGL((k_det_tensor<N, JP, T>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256), 0, st,
-                           a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
+        if (gx)
+            hipLaunchKernelGGL((k_det_tensor<N, JP, T, true>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256), 0,
+                               st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
+        else
+            hipLaunchKernelGGL((k_det_tensor<N, JP, T, false>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256), 0,
+                               st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)nullptr);
     }
     static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
         constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
@@ -156,12 +167,12 @@ template <int N, int JP, typename T> struct Impl {
     static void sq_err(s3_plan *p, const int32_t *idx, const void *val, int64_t nnz, double *part,
                        hipStream_t st) {
         auto a = tensor_args<T>(p, idx, val, nnz);
-        hipLaunchKernelGGL((k_sq_err_tensor<N, JP, T>), dim3(kReduceBlocks), dim3(256), 0, st, a,
+        hipLaunchKernelGGL((k_sq_err_tensor<N, JP, T>), dim3(sq_blocks(nnz)), dim3(256), 0, st, a,
                            (const T *)p->Gp, part);
     }
     static void predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *out, hipStream_t st) {
         auto a = tensor_args<T>(p, idx, nullptr, nnz);
-        hipLaunchKernelGGL((k_predict<N, JP, T>), dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, a,
+        hipLaunchKernelGGL((k_predict<N, JP, T>), dim3(grid_for(nnz, 256, 1ll << 30)), dim3(256), 0, st, a,
                            (const T *)p->Gp, (T *)out);
     }
     static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st) {
@@ -204,6 +215,17 @@ int padded_rank(int N, int Jmax) {
         for (int v : p4) if (Jmax <= v) return v;
     }
     return 0;
+}
+
+// event pair k around a dominant-kernel launch (profiling only)
+hipError_t prof_mark(s3_plan *p, size_t k, hipStream_t st) {
+    while (p->pev.size() <= k) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        p->pev.push_back(e);
+    }
+    return hipEventRecord(p->pev[k], st);
 }
 
 double eta_of(const s3_desc &d, int epoch) { return d.eta0 / (1.0 + d.mu * (double)epoch); }
@@ -252,10 +274,14 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
     const int64_t t0 = to[0], nt = to[1] - to[0];
     pad_core<T>(p, st);
     if (nt > 0) {
-        if (adj && gx == nullptr)
+        if (adj && gx == nullptr) {
             fill<T>(p->scr, nt * p->t_stride, 0.0, st);
-        else
+        } else {
+            const bool prof = p->prof && !adj;
+            if (prof) (void)prof_mark(p, p->pev_used++, st);
             p->ks.det_tensor(p, p->sorted_ids + t0, nt, gx, st);
+            if (prof) (void)prof_mark(p, p->pev_used++, st);
+        }
     }
     for (int m = 0; m < M; ++m) {
         const int64_t m0 = to[m + 1], nm = to[m + 2] - to[m + 1];
@@ -352,6 +378,7 @@ s3_status s3_plan_destroy(s3_plan *p) {
     if (!p) return S3_ERR_INVALID_ARG;
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
+    for (hipEvent_t e : p->pev) (void)hipEventDestroy(e);
     delete p;
     return S3_OK;
 }
@@ -419,7 +446,8 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
     for (int m = 0; m < M; ++m) p->cntV[m] = c.take<int32_t>((size_t)p->d.mat_cols[m]);
     p->Gp = c.take<T>((size_t)p->KP);
     p->flag = c.take<int32_t>(16);
-    p->red = c.take<double>(8 * kReduceBlocks);
+    p->n_red = std::max<int64_t>({(int64_t)2 * kReduceBlocks, sq_blocks(x_nnz), sq_blocks(t_nnz)});
+    p->red = c.take<double>((size_t)p->n_red);
     int64_t n_items = x_nnz;
     for (int m = 0; m < M; ++m) n_items += y_nnz[m];
     const int64_t B = p->d.batch;
@@ -444,7 +472,7 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
             p->grp[g].seg_row = c.take<int32_t>((size_t)std::max<int64_t>(nv, 1));
         }
         // per-batch scratch
-        const int64_t RJ = [&] { int64_t s = 0; for (int n = 0; n < N; ++n) s += p->d.rank[n]; return s; }();
+        const int64_t RJ = (int64_t)N * p->JP;  // gradient rows at a fixed JP stride
         p->RJ = RJ;
         p->t_stride = RJ + N + 2;
         const int64_t max_nt = std::min(B, x_nnz);
@@ -530,7 +558,7 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
         if (g < N) {
             ga.t_goff = goff;
             ga.t_coff = p->RJ + g;
-            goff += p->d.rank[g];
+            goff += p->JP;
             G.J = p->d.rank[g];
             G.rows = p->d.dims[g];
         } else {
@@ -637,17 +665,21 @@ template <typename T> s3_status loss_impl(s3_plan *p, double *out, hipStream_t s
     const int N = p->N, M = p->M;
     double *r = p->red;
     pad_core<T>(p, st);
-    p->ks.sq_err(p, p->b.x_idx, p->b.x_val, p->nX, r, st);                     // slot 0: tensor sse
-    hipLaunchKernelGGL(k_sq_rows<T>, dim3(kReduceBlocks), dim3(256), 0, st, (const T *)p->b.G, (int64_t)1,
-                       (int)p->K, (const int32_t *)nullptr, r + kReduceBlocks);  // slot 1: |G|^2
-    // slot 2: observed factor rows (accumulated over modes on host)
     std::vector<double> h(kReduceBlocks);
     double sse_t = 0, gg = 0, uu = 0, sse_m = 0, vv = 0;
-    p->h_red.resize(2 * kReduceBlocks);
-    HIPCHK(p, hipMemcpyAsync(p->h_red.data(), r, sizeof(double) * 2 * kReduceBlocks, hipMemcpyDeviceToHost, st));
+    {
+        const int64_t nb = sq_blocks(p->nX);
+        p->ks.sq_err(p, p->b.x_idx, p->b.x_val, p->nX, r, st);
+        p->h_red.resize((size_t)nb);
+        HIPCHK(p, hipMemcpyAsync(p->h_red.data(), r, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        for (int64_t i = 0; i < nb; ++i) sse_t += p->h_red[(size_t)i];
+    }
+    hipLaunchKernelGGL(k_sq_rows<T>, dim3(kReduceBlocks), dim3(256), 0, st, (const T *)p->b.G, (int64_t)1,
+                       (int)p->K, (const int32_t *)nullptr, r);
+    HIPCHK(p, hipMemcpyAsync(h.data(), r, sizeof(double) * kReduceBlocks, hipMemcpyDeviceToHost, st));
     HIPCHK(p, hipStreamSynchronize(st));
-    for (int i = 0; i < kReduceBlocks; ++i) sse_t += p->h_red[i];
-    for (int i = 0; i < kReduceBlocks; ++i) gg += p->h_red[kReduceBlocks + i];
+    for (double v : h) gg += v;
     for (int n = 0; n < N; ++n) {
         hipLaunchKernelGGL(k_sq_rows<T>, dim3(kReduceBlocks), dim3(256), 0, st, (const T *)p->b.U[n],
                            p->d.dims[n], p->d.rank[n], (const int32_t *)p->cnt[n], r);
@@ -699,8 +731,9 @@ template <typename T> s3_status rmse_impl(s3_plan *p, double *out, hipStream_t s
     if (p->nT == 0) { *out = 0.0; return S3_OK; }
     pad_core<T>(p, st);
     p->ks.sq_err(p, p->b.t_idx, p->b.t_val, p->nT, p->red, st);
-    std::vector<double> h(kReduceBlocks);
-    HIPCHK(p, hipMemcpyAsync(h.data(), p->red, sizeof(double) * kReduceBlocks, hipMemcpyDeviceToHost, st));
+    const int64_t nb = sq_blocks(p->nT);
+    std::vector<double> h((size_t)nb);
+    HIPCHK(p, hipMemcpyAsync(h.data(), p->red, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
     HIPCHK(p, hipStreamSynchronize(st));
     HIPCHK(p, hipGetLastError());
     double s = 0;
@@ -759,6 +792,7 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
     }
     if (mode == S3_DET_MINIBATCH) {
         if (!p->det_ready) return fail(p, S3_ERR_STATE, "det mode needs s3_bind with an item order");
+        p->pev_used = 0;
         HIPCHK(p, hipEventRecord(p->ev0, st));
         s3_status s = s3_det_batches(p, 0, p->n_batches, eta, stream);
         HIPCHK(p, hipEventRecord(p->ev1, st));
@@ -769,7 +803,12 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
         if (p->lf.H == 0) return fail(p, S3_ERR_UNSUPPORTED, "lock-free mode: rank too large for the LDS tables");
         HIPCHK(p, hipEventRecord(p->ev0, st));
         s3_status s;
-        auto round = [&](int64_t f, int64_t c, double e, hipStream_t s_) { p->ks.lf_tensor(p, f, c, e, s_); };
+        p->pev_used = 0;
+        auto round = [&](int64_t f, int64_t c, double e, hipStream_t s_) {
+            if (p->prof && c > 0) (void)prof_mark(p, p->pev_used++, s_);
+            p->ks.lf_tensor(p, f, c, e, s_);
+            if (p->prof && c > 0) (void)prof_mark(p, p->pev_used++, s_);
+        };
         if (p->tsize == 8) {
             pad_core<double>(p, st);
             s = lockfree_epoch<double>(p->lf, p->d, epoch, eta, (double *)p->Gp, st, p->err, round);
@@ -902,12 +941,29 @@ s3_status s3_sync_bf16(s3_plan *p, void *stream) {
     return fail(p, S3_ERR_UNSUPPORTED, "bf16 working copies are not built in this library");
 }
 
+s3_status s3_set_profiling(s3_plan *p, int32_t on) {
+    if (!p) return S3_ERR_INVALID_ARG;
+    p->prof = on != 0;
+    return S3_OK;
+}
+
 s3_status s3_last_epoch_profile(const s3_plan *cp, double *kernel_ms, int64_t *launches) {
     s3_plan *p = const_cast<s3_plan *>(cp);
     if (!p || !kernel_ms || !launches) return S3_ERR_INVALID_ARG;
-    if (!p->ev0) return S3_ERR_STATE;
-    float ms = 0.f;
+    if (!p->ev0) return fail(p, S3_ERR_STATE, "no epoch has run");
     HIPCHK(p, hipEventSynchronize(p->ev1));
+    if (p->prof && p->pev_used >= 2) {
+        double total = 0.0;
+        for (size_t k = 0; k + 1 < p->pev_used; k += 2) {
+            float ms = 0.f;
+            HIPCHK(p, hipEventElapsedTime(&ms, p->pev[k], p->pev[k + 1]));
+            total += ms;
+        }
+        *kernel_ms = total;
+        *launches = (int64_t)(p->pev_used / 2);
+        return S3_OK;
+    }
+    float ms = 0.f;
     HIPCHK(p, hipEventElapsedTime(&ms, p->ev0, p->ev1));
     *kernel_ms = ms;
     *launches = p->last_launches;

@@ -148,6 +148,9 @@ class S3Plan:
     def n_batches(self) -> int:
         return (self.n_items + self.desc.batch - 1) // self.desc.batch
 
+    def set_profiling(self, on: bool) -> None:
+        check(self.lib.s3_set_profiling(self.h, 1 if on else 0), self.h)
+
     def last_epoch_profile(self):
         ms = C.c_double()
         n = C.c_int64()
