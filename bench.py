@@ -57,7 +57,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed epochs before the timed ones")
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--mode", default="lockfree", choices=["lockfree", "det"])
-    ap.add_argument("--round-items", type=int, default=65536)
+    ap.add_argument("--round-items", type=int, default=262144)
+    ap.add_argument("--hot-rows", type=int, default=128)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,7 +86,7 @@ def main():
     log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {n_updates - p.n_train:,} matrix entries")
     order = item_order(p.n_items, args.seed, 0) if args.mode == "det" else None
     plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", batch=args.batch, order=order, damping=True,
-                               round_items=args.round_items, seed=args.seed)
+                               round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows)
     torch.cuda.synchronize()
     rmse0 = plan.rmse()
     log(f"bound; initial held-out RMSE {rmse0:.4f}")
@@ -147,6 +148,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.description}", "mode": args.mode,
                    "round_items": args.round_items if args.mode == "lockfree" else None,
+                   "hot_rows": args.hot_rows if args.mode == "lockfree" else None,
                    "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
                    "updates_per_epoch": n_updates, "parallelism": "single GPU"},
         "heldout_rmse": rmse, "heldout_rmse_init": rmse0, "rmse_epochs": E, "rmse_target": target,

@@ -109,6 +109,9 @@ typedef struct {
     int64_t batch;                       /* det mode: items per batch (>= 1) */
     int64_t round_items;                 /* lock-free: items per round (>= 1) */
     uint64_t seed;                       /* lock-free tile shuffle seed      */
+    int32_t hot_rows;                    /* lock-free: rows per mode kept in the
+                                            per-round hot tables (0: as many as
+                                            the LDS budget allows, <= 256)    */
 } s3_desc;
 
 /* Device buffers handed to s3_bind.  Values and parameters are `double` for

@@ -39,6 +39,7 @@ class S3Desc(C.Structure):
         ("dtype", C.c_int32), ("damping", C.c_int32),
         ("eta0", C.c_double), ("mu", C.c_double), ("lambda_reg", C.c_double), ("lambda_m", C.c_double),
         ("batch", C.c_int64), ("round_items", C.c_int64), ("seed", C.c_uint64),
+        ("hot_rows", C.c_int32),
     ]
 
 

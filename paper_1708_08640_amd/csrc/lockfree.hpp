@@ -18,9 +18,10 @@
 //          operands); at the end the workgroup writes its whole hot-row
 //          table and core partial to its own slot of a partials buffer
 //          (plain coalesced stores: no global atomics).
+//   k_lf_core_sum  sums the round's core partials in a fixed order.
 //   k_lf_apply  one workgroup per hot row (and per core chunk): sums the
-//          partials of every workgroup of the round in a fixed order and
-//          moves the row / the core once by the damped step
+//          hot-row partials of every workgroup of the round in a fixed order
+//          and moves the row / the core once by the damped step
 //          -eta sum g / max(1, k eta sum L).
 // "Hot" rows are the H most frequent rows of each mode and of each coupled
 // factor.  The paper lets one worker own the core, which every entry
@@ -245,6 +246,7 @@ struct LFApplyArgs {
     const void *tab_m[kMaxM];               // matrix tables [nwg_m][2][H][JP+1]
     int64_t nwg_m[kMaxM];
     const void *core_t;                     // tensor core partials [nwg_t][KP+2]
+    const void *core_sum;                   // their sum over the round [KP+2]
 };
 
 constexpr int kApplyThreads = 256;
@@ -260,6 +262,35 @@ template <typename T> S3_DEV void lf_block_sum(T *vals, int n, T *s_red) {
         __syncthreads();
     }
     for (int k = 0; k < n; ++k) vals[k] = s_red[k * kApplyThreads];
+}
+
+// Fixed-order sum of the round's per-workgroup core partials (and their
+// curvature and entry count): 16 consecutive elements per block, 16
+// workgroup phases per element, four independent running sums per thread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lf_core_sum(const T *__restrict__ core_t, int64_t nwg, int64_t cs,
+                                                     T *__restrict__ core_sum) {
+    __shared__ T s_part[16][17];
+    const int el = threadIdx.x & 15, ph = threadIdx.x >> 4;
+    const int64_t j = (int64_t)blockIdx.x * 16 + el;
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    if (j < cs) {
+        int64_t b = ph;
+        for (; b + 48 < nwg; b += 64) {
+            a0 += core_t[b * cs + j];
+            a1 += core_t[(b + 16) * cs + j];
+            a2 += core_t[(b + 32) * cs + j];
+            a3 += core_t[(b + 48) * cs + j];
+        }
+        for (; b < nwg; b += 16) a0 += core_t[b * cs + j];
+    }
+    s_part[ph][el] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (ph == 0 && j < cs) {
+        T t = T(0);
+        for (int q = 0; q < 16; ++q) t += s_part[q][el];
+        core_sum[j] = t;
+    }
 }
 
 // blocks [0, groups * H): one hot row each; blocks after: core chunks of
@@ -307,19 +338,13 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
         }
         return;
     }
-    // core
+    // core (the round's sums come from k_lf_core_sum)
     const int Js[4] = {J0, J1, J2, J3};
     int K = 1, KP = 1;
     for (int n = 0; n < N; ++n) { K *= Js[n]; KP *= JP; }
     const int j = (blockIdx.x - nrowblk) * kApplyThreads + tid;
-    const T *core = (const T *)a.core_t;
-    const size_t cs = (size_t)KP + 2;
-    // every thread needs the round's total core curvature and entry count
-    T LG = T(0), cnt = T(0);
-    for (int64_t b = 0; b < a.nwg_t; ++b) {
-        LG += core[b * cs + KP];
-        cnt += core[b * cs + KP + 1];
-    }
+    const T *cs = (const T *)a.core_sum;
+    const T LG = cs[KP], cnt = cs[KP + 1];
     if (j >= K || cnt == T(0)) return;
     int rem = j, pj = 0, mul = 1;
     for (int n = N - 1; n >= 0; --n) {
@@ -328,12 +353,10 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
         pj += jn * mul;
         mul *= JP;
     }
-    T s = T(0);
-    for (int64_t b = 0; b < a.nwg_t; ++b) s += core[b * cs + pj];
     const T Lsum = LG + cnt * reg_core;
     const T d = kappa * eta * Lsum;
     const T step = eta / (d > T(1) ? d : T(1));
-    const T gnew = G[j] - step * (s + cnt * reg_core * G[j]);
+    const T gnew = G[j] - step * (cs[pj] + cnt * reg_core * G[j]);
     G[j] = gnew;
     Gp[pj] = gnew;
 }
@@ -350,7 +373,7 @@ struct LockFreeState {
     int32_t *hot_slot[kMaxN + kMaxM] = {};
     int32_t *hot_row[kMaxN + kMaxM] = {};
     int64_t rows[kMaxN + kMaxM] = {};
-    void *tab_t = nullptr, *core_t = nullptr;
+    void *tab_t = nullptr, *core_t = nullptr, *core_sum = nullptr;
     void *tab_m[kMaxM] = {};
     uint64_t seed = 0;
     bool ready = false;
@@ -363,11 +386,13 @@ struct LockFreeState {
 
 constexpr size_t kLfLdsBudget = 64 * 1024;
 
-// hot rows per group so that the tensor kernel's LDS fits the budget (0: none fits)
-inline int lf_hot_rows(int N, int JP, size_t tsize) {
+// hot rows per group: the requested count (power of two, <= 256) or, for 0,
+// the largest that lets the tensor kernel's LDS fit the budget (0: none fits)
+inline int lf_hot_rows(int N, int JP, size_t tsize, int requested) {
     const size_t staging = ((size_t)kTile * N * JP + 2) * tsize;
     for (int H = 256; H >= 16; H /= 2)
-        if (staging + (size_t)N * H * (JP + 1) * tsize <= kLfLdsBudget) return H;
+        if ((requested <= 0 || H <= requested) && staging + (size_t)N * H * (JP + 1) * tsize <= kLfLdsBudget)
+            return H;
     return 0;
 }
 
@@ -378,7 +403,7 @@ void lockfree_layout(LockFreeState &s, C &c, int N, int M, const s3_desc &d, int
     s.M = M;
     s.JP = JP;
     s.KP = KP;
-    s.H = lf_hot_rows(N, JP, sizeof(T));
+    s.H = lf_hot_rows(N, JP, sizeof(T), d.hot_rows);
     const int H = std::max(s.H, 1);
     int64_t n_items = x_nnz;
     for (int m = 0; m < M; ++m) n_items += y_nnz[m];
@@ -400,6 +425,7 @@ void lockfree_layout(LockFreeState &s, C &c, int N, int M, const s3_desc &d, int
     }
     s.tab_t = c.template take<T>((size_t)s.max_t_wg * N * H * (JP + 1));
     s.core_t = c.template take<T>((size_t)s.max_t_wg * (KP + 2));
+    s.core_sum = c.template take<T>((size_t)KP + 2);
 }
 
 // pick the H most frequent rows of every group (host side, from the counts)
@@ -460,6 +486,7 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
     }
     s.apply.tab_t = s.tab_t;
     s.apply.core_t = s.core_t;
+    s.apply.core_sum = s.core_sum;
     s.ready = true;
     return S3_OK;
 }
@@ -540,6 +567,11 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
                                s.b.y_col[m], (const T *)s.b.y_val[m], s.y_nnz[m], (T *)s.b.U[c], (T *)s.b.V[m],
                                J[c], s.cntV[m], (T)d.lambda_m, (T)d.lambda_reg, L, c, N + m, (T)eta, kappa);
         }
+        if (t1 > t0)
+            hipLaunchKernelGGL(k_lf_core_sum<T>, dim3((unsigned)((s.KP + 2 + 15) / 16)), dim3(256), 0, st,
+                               (const T *)s.core_t, t1 - t0, s.KP + 2, (T *)s.core_sum);
+        else
+            hipLaunchKernelGGL(k_fill<T>, dim3(4), dim3(256), 0, st, (T *)s.core_sum, s.KP + 2, T(0));
         const int64_t blocks = (int64_t)(N + M) * s.H + (K + kApplyThreads - 1) / kApplyThreads;
         auto kern = (N == 3) ? k_lf_apply<3, T> : k_lf_apply<4, T>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kApplyThreads), 0, st, s.apply, s.H, s.JP,

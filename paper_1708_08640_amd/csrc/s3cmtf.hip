@@ -345,7 +345,7 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     if (d.n_mat < 0 || d.n_mat > S3_MAX_MATRICES) return S3_ERR_INVALID_ARG;
     if (d.dtype != S3_F64 && d.dtype != S3_F32 && d.dtype != S3_BF16) return S3_ERR_UNSUPPORTED;
     if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
-    if (d.batch < 1 || d.round_items < 1) return S3_ERR_INVALID_ARG;
+    if (d.batch < 1 || d.round_items < 1 || d.hot_rows < 0 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
     if (!(d.eta0 > 0) || !(d.mu >= 0) || !(d.lambda_reg >= 0) || !(d.lambda_m >= 0)) return S3_ERR_INVALID_ARG;
     int Jmax = 0;
     for (int n = 0; n < d.order; ++n) {

@@ -21,7 +21,7 @@ def _oracle_rmse(cfg, p, ref, epochs, seed=7):
 
 
 @pytest.mark.parametrize("name,dtype,round_items,epochs,over", [
-    ("cfg1", "f64", 256, 25, dict(planted=True)),
+    ("cfg1", "f64", 256, 40, dict(planted=True)),
     ("cfg2_slice", "f32", 4096, 3, dict()),
 ])
 def test_lockfree_rmse_tracks_sequential_sgd(name, dtype, round_items, epochs, over):
