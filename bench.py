@@ -37,6 +37,32 @@ def tensor_entry_flops(ranks):
     return 6 * K + 10 * sum(ranks)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp"):
+        with open(os.path.join(ROOT, "paper_1708_08640_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_lf_tensor_cfg2_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("#", " ", "|")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256_16") != kernel_source_hash() or kernel not in fields.get("kernel", ""):
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(cfg, p, U, G, V, sample, seed):
     import oracle
     from synth import item_order
@@ -63,6 +89,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (3 times), to calibrate the HBM "
+                         "byte counters of a profiler run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -70,8 +99,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "copies": 3}), flush=True)
+        return
 
     from paper_1708_08640_amd import S3Plan
     from synth import get_config, init_params, item_order, make_problem
@@ -131,7 +170,8 @@ def main():
     roofline = {
         "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_tensor",
         "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None, "traffic": None,
+        "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
+        "traffic": profiled_traffic("k_lf_tensor") if args.mode == "lockfree" and cfg.name == "cfg2_zipf_10m" else None,
         "flops_per_entry": tensor_entry_flops(cfg.ranks), "launches": launches,
         "avg_launch_ms": kernel_ms / max(launches, 1), "kernel_share_of_epoch": kernel_ms / (t1 - t0) / 1e3,
     }
