@@ -111,7 +111,8 @@ typedef struct {
     uint64_t seed;                       /* lock-free tile shuffle seed      */
     int32_t hot_rows;                    /* lock-free: rows per mode kept in the
                                             per-round hot tables (0: as many as
-                                            the LDS budget allows, <= 256)    */
+                                            the LDS budget allows, <= 256; -1:
+                                            none, every row is updated at once) */
 } s3_desc;
 
 /* Device buffers handed to s3_bind.  Values and parameters are `double` for

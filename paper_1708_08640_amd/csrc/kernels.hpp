@@ -205,14 +205,16 @@ __global__ void k_pad_core(const T *__restrict__ G, T *__restrict__ Gp, int N, i
 
 // ------------------------------------------------------------- row loading
 
-template <int N, int JP, typename T>
+// EXACT: every rank equals JP, so rows load without predicates (the
+// compiler then merges them into wide vector loads)
+template <int N, int JP, typename T, bool EXACT = false>
 S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t (&rows)[N]) {
 #pragma unroll
     for (int n = 0; n < N; ++n) {
         rows[n] = A.idx[(int64_t)n * A.nnz + e];
-        const T *r = A.U[n] + (int64_t)rows[n] * A.J[n];
+        const T *r = A.U[n] + (int64_t)rows[n] * (EXACT ? JP : A.J[n]);
 #pragma unroll
-        for (int k = 0; k < JP; ++k) u[n][k] = (k < A.J[n]) ? r[k] : T(0);
+        for (int k = 0; k < JP; ++k) u[n][k] = (EXACT || k < A.J[n]) ? r[k] : T(0);
     }
 }
 

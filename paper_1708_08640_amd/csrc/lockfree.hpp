@@ -4,7 +4,8 @@
 // An epoch is a sequence of rounds; a round takes a slice of 256-entry
 // tiles (tensor and coupled-matrix tiles, in a per-epoch shuffled tile
 // order) and runs:
-//   k_lf_tensor / k_lf_matrix  one workgroup per tile, one lane per entry;
+//   k_lf_tensor  one workgroup per tile (tensor tiles, then the round's
+//          coupled-matrix tiles in the same launch), one lane per entry;
 //          each lane reads the current factor rows without locks, and for
 //          each row it moves:
 //            cold row -> at once, u <- u - eta g / max(1, k eta L) written
@@ -14,8 +15,9 @@
 //                        one SGD step)
 //            hot row  -> gradient and curvature summed in an LDS table of
 //                        the workgroup
-//          the tile's core gradient is summed in registers (LDS-staged
-//          operands); at the end the workgroup writes its whole hot-row
+//          the tile's core gradient is one small GEMM on the FP32 matrix
+//          cores (LDS-staged operands); at the end the workgroup writes its
+//          whole hot-row
 //          table and core partial to its own slot of a partials buffer
 //          (plain coalesced stores: no global atomics).
 //   k_lf_core_sum  sums the round's core partials in a fixed order.
@@ -33,6 +35,7 @@
 #include <cmath>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -43,6 +46,8 @@ constexpr int kTile = 256;
 
 template <typename T> struct LFArgs {
     const int32_t *hot_slot[kMaxN + kMaxM];  // row -> slot in [0, H) or -1
+    const uint2 *meta_slot;  // per tensor entry: its rows' hot slots, int16 each (-1: cold)
+    const T *meta_reg;       // per tensor entry and mode: lambda_reg / |Omega^{n,i_n}|, [N][nnz]
     T *tab_out;        // per-workgroup hot tables: [wg][groups][H][JP + 1]
     T *core_out;       // per-workgroup core partials: [wg][KP + 2] (tensor only)
     int H;
@@ -65,14 +70,174 @@ template <int JP, int TAIL> constexpr int lf_split() {
     return best;
 }
 
+// ------------------------------------------------------------------ matrix
+
+// Coupled-matrix tiles of one round; they run in the same launch as the
+// tensor tiles (blocks after the tensor blocks), in matrix order.
+template <typename T> struct LFMatArgs {
+    const int32_t *row[kMaxM];
+    const int32_t *col[kMaxM];
+    const T *val[kMaxM];
+    int64_t nnz[kMaxM];
+    T *Uc[kMaxM];
+    T *V[kMaxM];
+    int J[kMaxM];
+    const int32_t *cntV[kMaxM];
+    int64_t n_tiles[kMaxM];   // tiles of the matrix
+    int64_t tile_base[kMaxM]; // first permuted tile of this round
+    int64_t n_blocks[kMaxM];  // tiles of this round
+    uint64_t pa[kMaxM], pb[kMaxM];
+    T *tab_out[kMaxM];        // [wg][2][H][JP + 1]
+    const uint32_t *meta_slot[kMaxM];  // per entry: u-row and V-row hot slots (int16 each, -1 cold)
+    const T *meta_rv[kMaxM];           // per entry: lambda_m lambda_reg / |Omega_Y^{2,k}|
+    int gu[kMaxM], gv[kMaxM];
+    int M;
+    T lambda_m;
+};
+
+template <int JP, typename T, bool EXACT>
+S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFArgs<T> &L, T eta, T kappa,
+                           T *s_tab) {
+    const int tid = threadIdx.x;
+    const int tabn = 2 * L.H * (JP + 1);
+    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
+    __syncthreads();
+    const int64_t tile = lf_perm(Y.tile_base[m] + blk, Y.pa[m], Y.pb[m], Y.n_tiles[m]);
+    const int64_t e = tile * kTile + tid;
+    const int J = EXACT ? JP : Y.J[m];
+    if (e < Y.nnz[m]) {
+        const int32_t r = Y.row[m][e], cl = Y.col[m][e];
+        const uint32_t ms = Y.meta_slot[m][e];
+        T *u = Y.Uc[m] + (int64_t)r * J;
+        T *v = Y.V[m] + (int64_t)cl * J;
+        T ur[JP], vr[JP];
+        T yh = T(0), uu = T(0), vv = T(0);
+#pragma unroll
+        for (int k = 0; k < JP; ++k) {
+            ur[k] = (EXACT || k < J) ? u[k] : T(0);
+            vr[k] = (EXACT || k < J) ? v[k] : T(0);
+            yh = fmaT(ur[k], vr[k], yh);
+            uu = fmaT(ur[k], ur[k], uu);
+            vv = fmaT(vr[k], vr[k], vv);
+        }
+        const T q = -Y.lambda_m * (Y.val[m][e] - yh);
+        const T rv = Y.meta_rv[m][e];
+        const T Lu = Y.lambda_m * vv, Lv = fmaT(Y.lambda_m, uu, rv);
+        const int su = (int)(int16_t)(ms & 0xffffu);
+        const int sv = (int)(int16_t)(ms >> 16);
+        if (su >= 0) {
+            T *t = s_tab + (size_t)su * (JP + 1);
+#pragma unroll
+            for (int k = 0; k < JP; ++k) atomicAdd(&t[k], q * vr[k]);
+            atomicAdd(&t[JP], Lu);
+        } else {
+            const T d = kappa * eta * Lu;
+            const T step = eta / (d > T(1) ? d : T(1));
+#pragma unroll
+            for (int k = 0; k < JP; ++k)
+                if (EXACT || k < J) u[k] = ur[k] - step * q * vr[k];
+        }
+        if (sv >= 0) {
+            T *t = s_tab + ((size_t)L.H + sv) * (JP + 1);
+#pragma unroll
+            for (int k = 0; k < JP; ++k) atomicAdd(&t[k], fmaT(q, ur[k], rv * vr[k]));
+            atomicAdd(&t[JP], Lv);
+        } else {
+            const T d = kappa * eta * Lv;
+            const T step = eta / (d > T(1) ? d : T(1));
+#pragma unroll
+            for (int k = 0; k < JP; ++k)
+                if (EXACT || k < J) v[k] = vr[k] - step * fmaT(q, ur[k], rv * vr[k]);
+        }
+    }
+    __syncthreads();
+    T *tab = Y.tab_out[m] + (size_t)blk * tabn;
+    for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
+}
+
+// Core gradient of one 256-entry tile on the FP32 matrix cores:
+//   C[j1][tau] = sum_t (q u^(1))_t[j1] * (u^(2) o ... o u^(N))_t[tau]
+// as a (16 x 256) x (256 x 16 n-tiles) product with v_mfma_f32_16x16x4f32
+// (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 (l / 16) + r][l % 16]
+// in lane l, register r).  M = j1 (JP <= 16, zero padded), K = the tile's
+// entries, N = tail index tau; wave w takes n-tiles w, w + 4, ...; the
+// Khatri-Rao operand is formed from the LDS-staged rows as it is consumed.
+typedef float s3_v4f __attribute__((ext_vector_type(4)));
+
+template <int N, int JP>
+S3_DEV void lf_core_tile_mfma(const float *s_q, const float *s_u, float *core) {
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
+    constexpr int NW = kTile / kWave;                    // waves per tile
+    constexpr int TPW = (NT + NW - 1) / NW;              // n-tiles per wave (max)
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int i16 = lane & 15, kq = lane >> 4;
+    s3_v4f acc[TPW];
+    int tj[TPW][N - 1];
+    bool tv[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        acc[q] = s3_v4f{0.f, 0.f, 0.f, 0.f};
+        const int tau = 16 * (wv + NW * q) + i16;
+        tv[q] = (wv + NW * q < NT) && tau < TAIL;
+        int r = tv[q] ? tau : 0;
+#pragma unroll
+        for (int n = N - 2; n >= 0; --n) { tj[q][n] = r % JP; r /= JP; }
+    }
+    for (int k0 = 0; k0 < kTile; k0 += 4) {
+        const int t = k0 + kq;
+        const float a = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            if (wv + NW * q < NT) {  // uniform over the wave
+                float b = s_u[(t * (N - 1)) * JP + tj[q][0]];
+#pragma unroll
+                for (int n = 1; n < N - 1; ++n) b *= s_u[(t * (N - 1) + n) * JP + tj[q][n]];
+                b = tv[q] ? b : 0.f;
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        if (!(wv + NW * q < NT)) continue;
+        const int tau = 16 * (wv + NW * q) + i16;
+        if (tau >= TAIL) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j1 = 4 * kq + r;
+            if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[q][r];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ tensor
 
-template <int N, int JP, typename T>
-__global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *__restrict__ Gp, LFArgs<T> L,
-                                                     T eta, T kappa) {
+// Blocks [0, n_tensor): tensor tiles.  Blocks after: the round's matrix
+// tiles, matrix by matrix.
+// minimum waves per SIMD requested from the register allocator: 3 for cores
+// of up to 1,024 entries (fits in 168 VGPRs without spilling, and matches the
+// three 256-thread workgroups per CU the LDS allows), 1 otherwise
+template <int N, int JP> constexpr int lf_min_waves() { return ((N == 3 ? JP * JP * JP : JP * JP * JP * JP) <= 1024) ? 3 : 1; }
+
+template <int N, int JP, typename T, bool EXACT>
+__global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
+                                                                          LFArgs<T> L, LFMatArgs<T> Y,
+                                                                          int64_t n_tensor, T eta, T kappa) {
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
     constexpr int KP = JP * TAIL;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    if ((int64_t)blockIdx.x >= n_tensor) {
+        int64_t blk = (int64_t)blockIdx.x - n_tensor;
+        for (int m = 0; m < Y.M; ++m) {
+            if (blk < Y.n_blocks[m]) {
+                lf_matrix_tile<JP, T, EXACT>(Y, m, blk, L, eta, kappa, (T *)smem_raw);
+                return;
+            }
+            blk -= Y.n_blocks[m];
+        }
+        return;
+    }
     T *s_tab = (T *)smem_raw;                         // [N][H][JP + 1]
     T *s_q = s_tab + (size_t)N * L.H * (JP + 1);     // [kTile][JP]  q * u^(1)
     T *s_u = s_q + kTile * JP;                        // [kTile][N - 1][JP]
@@ -88,15 +253,19 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
     if (e < A.nnz) {
         T u[N][JP], w[N][JP];
         int32_t rows[N];
-        load_rows<N, JP, T>(A, e, u, rows);
+        load_rows<N, JP, T, EXACT>(A, e, u, rows);
         const T xv = A.val[e];
+        const uint2 ms = L.meta_slot[e];
+        T regs[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) regs[n] = L.meta_reg[(int64_t)n * A.nnz + e];
         T xhat;
         contract<N, JP, T>(Gp, u, w, xhat);
         const T q = -(xv - xhat);
         T LG = T(1);
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            const T reg = A.lambda_reg / (T)A.cnt[n][rows[n]];
+            const T reg = regs[n];
             T ww = T(0), uu = T(0);
 #pragma unroll
             for (int k = 0; k < JP; ++k) {
@@ -105,7 +274,8 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
             }
             LG *= uu;
             const T ell = ww + reg;
-            const int slot = L.hot_slot[n][rows[n]];
+            const uint32_t half = (n < 2) ? ms.x : ms.y;
+            const int slot = (int)(int16_t)((n & 1) ? (half >> 16) : (half & 0xffffu));
             if (slot >= 0) {
                 T *t = s_tab + ((size_t)n * L.H + slot) * (JP + 1);
 #pragma unroll
@@ -114,10 +284,10 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
             } else {
                 const T d = kappa * eta * ell;
                 const T step = eta / (d > T(1) ? d : T(1));
-                T *r = A.U[n] + (int64_t)rows[n] * A.J[n];
+                T *r = A.U[n] + (int64_t)rows[n] * (EXACT ? JP : A.J[n]);
 #pragma unroll
                 for (int k = 0; k < JP; ++k)
-                    if (k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
+                    if (EXACT || k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
             }
         }
         // stage the core-gradient operands
@@ -138,93 +308,39 @@ __global__ __launch_bounds__(kTile) void k_lf_tensor(TensorArgs<T> A, const T *_
             for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = T(0);
     }
     __syncthreads();
-    // core gradient of this tile: work item = (tail index tau over modes
-    // 2..N, slice of JS consecutive mode-1 indices); all threads take part
-    constexpr int SPLIT = lf_split<JP, TAIL>();
-    constexpr int JS = JP / SPLIT;
     T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
-    for (int item = tid; item < TAIL * SPLIT; item += kTile) {
-        const int tau = item % TAIL, j0 = (item / TAIL) * JS;
-        int tj[N - 1];
-        int r = tau;
+    if constexpr (std::is_same<T, float>::value) {
+        lf_core_tile_mfma<N, JP>(s_q, s_u, core);
+    } else {
+        // core gradient of this tile on the VALU: work item = (tail index tau
+        // over modes 2..N, slice of JS consecutive mode-1 indices)
+        constexpr int SPLIT = lf_split<JP, TAIL>();
+        constexpr int JS = JP / SPLIT;
+        for (int item = tid; item < TAIL * SPLIT; item += kTile) {
+            const int tau = item % TAIL, j0 = (item / TAIL) * JS;
+            int tj[N - 1];
+            int r = tau;
 #pragma unroll
-        for (int n = N - 2; n >= 0; --n) { tj[n] = r % JP; r /= JP; }
-        T acc[JS];
+            for (int n = N - 2; n >= 0; --n) { tj[n] = r % JP; r /= JP; }
+            T acc[JS];
 #pragma unroll
-        for (int k = 0; k < JS; ++k) acc[k] = T(0);
-        for (int t = 0; t < kTile; ++t) {
-            T p = s_u[((size_t)t * (N - 1)) * JP + tj[0]];
+            for (int k = 0; k < JS; ++k) acc[k] = T(0);
+            for (int t = 0; t < kTile; ++t) {
+                T p = s_u[((size_t)t * (N - 1)) * JP + tj[0]];
 #pragma unroll
-            for (int n = 1; n < N - 1; ++n) p *= s_u[((size_t)t * (N - 1) + n) * JP + tj[n]];
+                for (int n = 1; n < N - 1; ++n) p *= s_u[((size_t)t * (N - 1) + n) * JP + tj[n]];
 #pragma unroll
-            for (int k = 0; k < JS; ++k) acc[k] = fmaT(s_q[t * JP + j0 + k], p, acc[k]);
+                for (int k = 0; k < JS; ++k) acc[k] = fmaT(s_q[t * JP + j0 + k], p, acc[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < JS; ++k) core[(size_t)(j0 + k) * TAIL + tau] = acc[k];
         }
-#pragma unroll
-        for (int k = 0; k < JS; ++k) core[(size_t)(j0 + k) * TAIL + tau] = acc[k];
     }
     if (tid == 0) {
         core[KP] = s_misc[0];
         core[KP + 1] = s_misc[1];
     }
     // the workgroup's hot-row table, written densely
-    T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
-    for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
-}
-
-// ------------------------------------------------------------------ matrix
-
-template <typename T>
-__global__ __launch_bounds__(kTile) void k_lf_matrix(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
-                                                    const T *__restrict__ val, int64_t nnz, T *__restrict__ Uc,
-                                                    T *__restrict__ V, int J, const int32_t *__restrict__ cntV,
-                                                    T lambda_m, T lambda_reg, LFArgs<T> L, int gu, int gv,
-                                                    T eta, T kappa) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *s_tab = (T *)smem_raw;  // [2][H][JP + 1]: coupled-mode rows, then V rows
-    const int JP = L.JP;
-    const int tid = threadIdx.x;
-    const int tabn = 2 * L.H * (JP + 1);
-    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
-    __syncthreads();
-    const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
-    const int64_t e = tile * kTile + tid;
-    if (e < nnz) {
-        T *u = Uc + (int64_t)row[e] * J;
-        T *v = V + (int64_t)col[e] * J;
-        T ur[16], vr[16];
-        T yh = T(0), uu = T(0), vv = T(0);
-        for (int k = 0; k < J; ++k) {
-            ur[k] = u[k];
-            vr[k] = v[k];
-            yh = fmaT(ur[k], vr[k], yh);
-            uu = fmaT(ur[k], ur[k], uu);
-            vv = fmaT(vr[k], vr[k], vv);
-        }
-        const T q = -lambda_m * (val[e] - yh);
-        const T rv = lambda_m * lambda_reg / (T)cntV[col[e]];
-        const T Lu = lambda_m * vv, Lv = fmaT(lambda_m, uu, rv);
-        const int su = L.hot_slot[gu][row[e]];
-        const int sv = L.hot_slot[gv][col[e]];
-        if (su >= 0) {
-            T *t = s_tab + (size_t)su * (JP + 1);
-            for (int k = 0; k < J; ++k) atomicAdd(&t[k], q * vr[k]);
-            atomicAdd(&t[JP], Lu);
-        } else {
-            const T d = kappa * eta * Lu;
-            const T step = eta / (d > T(1) ? d : T(1));
-            for (int k = 0; k < J; ++k) u[k] = ur[k] - step * q * vr[k];
-        }
-        if (sv >= 0) {
-            T *t = s_tab + ((size_t)L.H + sv) * (JP + 1);
-            for (int k = 0; k < J; ++k) atomicAdd(&t[k], fmaT(q, ur[k], rv * vr[k]));
-            atomicAdd(&t[JP], Lv);
-        } else {
-            const T d = kappa * eta * Lv;
-            const T step = eta / (d > T(1) ? d : T(1));
-            for (int k = 0; k < J; ++k) v[k] = vr[k] - step * fmaT(q, ur[k], rv * vr[k]);
-        }
-    }
-    __syncthreads();
     T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
     for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
 }
@@ -251,17 +367,22 @@ struct LFApplyArgs {
 
 constexpr int kApplyThreads = 256;
 
-// fixed-order tree sum over the block of n values per thread (n <= 17)
+// fixed-order sum over the block of n values per thread (n <= 17): a
+// butterfly inside each wavefront, then the wavefronts in order
 template <typename T> S3_DEV void lf_block_sum(T *vals, int n, T *s_red) {
-    const int tid = threadIdx.x;
-    for (int k = 0; k < n; ++k) s_red[k * kApplyThreads + tid] = vals[k];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    constexpr int NW = kApplyThreads / kWave;
+#pragma unroll
+    for (int k = 0; k < 17; ++k)
+        if (k < n) vals[k] = wave_sum(vals[k]);
+    if (lane == 0)
+        for (int k = 0; k < n; ++k) s_red[k * NW + wv] = vals[k];
     __syncthreads();
-    for (int w = kApplyThreads / 2; w > 0; w >>= 1) {
-        if (tid < w)
-            for (int k = 0; k < n; ++k) s_red[k * kApplyThreads + tid] += s_red[k * kApplyThreads + tid + w];
-        __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        T t = T(0);
+        for (int w = 0; w < NW; ++w) t += s_red[k * NW + w];
+        vals[k] = t;
     }
-    for (int k = 0; k < n; ++k) vals[k] = s_red[k * kApplyThreads];
 }
 
 // Fixed-order sum of the round's per-workgroup core partials (and their
@@ -299,7 +420,7 @@ template <int N, typename T>
 __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H, int JP, T *__restrict__ G,
                                                             T *__restrict__ Gp, int J0, int J1, int J2, int J3,
                                                             T reg_core, T eta, T kappa) {
-    __shared__ T s_red[17 * kApplyThreads];
+    __shared__ T s_red[17 * (kApplyThreads / kWave)];
     const int tid = threadIdx.x;
     const int nrowblk = a.groups * H;
     if ((int)blockIdx.x < nrowblk) {
@@ -307,6 +428,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
         const int row = a.hot_row[g][slot];
         if (row < 0) return;  // uniform over the block
         T acc[17];
+#pragma unroll
         for (int k = 0; k < 17; ++k) acc[k] = T(0);
         const size_t W = (size_t)JP + 1;
         if (g < N) {
@@ -332,7 +454,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
             const T step = eta / (d > T(1) ? d : T(1));
             T *p = (T *)a.P[g] + (int64_t)row * a.J[g];
             T gk = T(0);
-            for (int k = 0; k < JP; ++k)
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
                 if (k == tid) gk = acc[k];
             p[tid] -= step * gk;
         }
@@ -361,6 +484,43 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
     Gp[pj] = gnew;
 }
 
+// ---------------------------------------------------------------- metadata
+
+// Per-entry stream built once at bind time, read coalesced by the round
+// kernels instead of three random count/slot lookups per entry and mode.
+struct LFMetaSrc {
+    const int32_t *hot_slot[kMaxN + kMaxM];
+    const int32_t *cnt[kMaxN];
+};
+
+template <typename T>
+__global__ void k_lf_meta_tensor(const int32_t *__restrict__ idx, int64_t nnz, int N, LFMetaSrc src, T lambda_reg,
+                                  uint2 *__restrict__ slot_out, T *__restrict__ reg_out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t h[2] = {0xffffffffu, 0xffffffffu};
+        for (int n = 0; n < N; ++n) {
+            const int32_t row = idx[(int64_t)n * nnz + e];
+            const uint32_t sl = (uint32_t)(uint16_t)(int16_t)src.hot_slot[n][row];
+            h[n >> 1] = (n & 1) ? ((h[n >> 1] & 0xffffu) | (sl << 16)) : ((h[n >> 1] & 0xffff0000u) | sl);
+            reg_out[(int64_t)n * nnz + e] = lambda_reg / (T)src.cnt[n][row];
+        }
+        slot_out[e] = make_uint2(h[0], h[1]);
+    }
+}
+
+template <typename T>
+__global__ void k_lf_meta_matrix(const int32_t *__restrict__ row, const int32_t *__restrict__ col, int64_t nnz,
+                                 const int32_t *__restrict__ slot_u, const int32_t *__restrict__ slot_v,
+                                 const int32_t *__restrict__ cntV, T lm_lreg, uint32_t *__restrict__ slot_out,
+                                 T *__restrict__ rv_out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t su = (uint32_t)(uint16_t)(int16_t)slot_u[row[e]];
+        const uint32_t sv = (uint32_t)(uint16_t)(int16_t)slot_v[col[e]];
+        slot_out[e] = su | (sv << 16);
+        rv_out[e] = lm_lreg / (T)cntV[col[e]];
+    }
+}
+
 // ------------------------------------------------------------------- state
 
 struct LockFreeState {
@@ -374,6 +534,10 @@ struct LockFreeState {
     int32_t *hot_row[kMaxN + kMaxM] = {};
     int64_t rows[kMaxN + kMaxM] = {};
     void *tab_t = nullptr, *core_t = nullptr, *core_sum = nullptr;
+    uint2 *meta_slot = nullptr;
+    void *meta_reg = nullptr;
+    uint32_t *meta_mslot[kMaxM] = {};
+    void *meta_rv[kMaxM] = {};
     void *tab_m[kMaxM] = {};
     uint64_t seed = 0;
     bool ready = false;
@@ -382,17 +546,24 @@ struct LockFreeState {
     LFApplyArgs apply{};
     const int32_t *cntV[kMaxM] = {};
     s3_buffers b{};
+    // this round's matrix tiles (set by lockfree_epoch before the launch)
+    int64_t m_base[kMaxM] = {}, m_count[kMaxM] = {};
+    uint64_t mpa[kMaxM] = {}, mpb[kMaxM] = {};
+    int mat_mode[kMaxM] = {};
+    int mat_J[kMaxM] = {};
+    double lambda_m = 0.0;
 };
 
 constexpr size_t kLfLdsBudget = 64 * 1024;
 
 // hot rows per group: the requested count (power of two, <= 256) or, for 0,
-// the largest that lets the tensor kernel's LDS fit the budget (0: none fits)
+// the largest that lets the tensor kernel's LDS fit the budget (0: none
+// fits).  A negative request keeps a minimal table but marks no row hot.
 inline int lf_hot_rows(int N, int JP, size_t tsize, int requested) {
     const size_t staging = ((size_t)kTile * N * JP + 2) * tsize;
     for (int H = 256; H >= 16; H /= 2)
         if ((requested <= 0 || H <= requested) && staging + (size_t)N * H * (JP + 1) * tsize <= kLfLdsBudget)
-            return H;
+            return requested < 0 ? std::min(H, 16) : H;
     return 0;
 }
 
@@ -424,6 +595,12 @@ void lockfree_layout(LockFreeState &s, C &c, int N, int M, const s3_desc &d, int
         s.tab_m[m] = c.template take<T>((size_t)s.max_m_wg[m] * 2 * H * (JP + 1));
     }
     s.tab_t = c.template take<T>((size_t)s.max_t_wg * N * H * (JP + 1));
+    s.meta_slot = c.template take<uint2>((size_t)x_nnz);
+    s.meta_reg = c.template take<T>((size_t)x_nnz * N);
+    for (int m = 0; m < M; ++m) {
+        s.meta_mslot[m] = c.template take<uint32_t>((size_t)std::max<int64_t>(y_nnz[m], 1));
+        s.meta_rv[m] = c.template take<T>((size_t)std::max<int64_t>(y_nnz[m], 1));
+    }
     s.core_t = c.template take<T>((size_t)s.max_t_wg * (KP + 2));
     s.core_sum = c.template take<T>((size_t)KP + 2);
 }
@@ -442,6 +619,11 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
         s.cntV[m] = cntV[m];
     }
     s.seed = d.seed;
+    s.lambda_m = d.lambda_m;
+    for (int m = 0; m < M; ++m) {
+        s.mat_mode[m] = d.mat_mode[m];
+        s.mat_J[m] = d.rank[d.mat_mode[m]];
+    }
     s.n_rounds = std::max<int64_t>(1, (s.n_items + d.round_items - 1) / d.round_items);
     s.t_tiles = (nX + kTile - 1) / kTile;
     for (int m = 0; m < M; ++m) s.m_tiles[m] = (y_nnz[m] + kTile - 1) / kTile;
@@ -457,7 +639,7 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
         }
         std::vector<int32_t> order((size_t)R);
         std::iota(order.begin(), order.end(), 0);
-        const int64_t take = std::min<int64_t>(s.H, R);
+        const int64_t take = d.hot_rows < 0 ? 0 : std::min<int64_t>(s.H, R);
         std::partial_sort(order.begin(), order.begin() + take, order.end(), [&](int32_t a, int32_t b) {
             return h[a] != h[b] ? h[a] > h[b] : a < b;
         });
@@ -487,6 +669,17 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
     s.apply.tab_t = s.tab_t;
     s.apply.core_t = s.core_t;
     s.apply.core_sum = s.core_sum;
+    // per-entry metadata streams
+    LFMetaSrc src{};
+    for (int g = 0; g < N + M; ++g) src.hot_slot[g] = s.hot_slot[g];
+    for (int n = 0; n < N; ++n) src.cnt[n] = cnt[n];
+    hipLaunchKernelGGL(k_lf_meta_tensor<T>, dim3(4096), dim3(256), 0, st, buf->x_idx, nX, N, src, (T)d.lambda_reg,
+                       s.meta_slot, (T *)s.meta_reg);
+    for (int m = 0; m < M; ++m)
+        if (y_nnz[m] > 0)
+            hipLaunchKernelGGL(k_lf_meta_matrix<T>, dim3(4096), dim3(256), 0, st, buf->y_row[m], buf->y_col[m],
+                               y_nnz[m], s.hot_slot[d.mat_mode[m]], s.hot_slot[N + m], cntV[m],
+                               (T)(d.lambda_m * d.lambda_reg), s.meta_mslot[m], (T *)s.meta_rv[m]);
     s.ready = true;
     return S3_OK;
 }
@@ -496,6 +689,8 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
     for (int g = 0; g < s.N + s.M; ++g) L.hot_slot[g] = s.hot_slot[g];
     L.tab_out = tab;
     L.core_out = core;
+    L.meta_slot = s.meta_slot;
+    L.meta_reg = (const T *)s.meta_reg;
     L.H = s.H;
     L.JP = s.JP;
     L.n_tiles = n_tiles;
@@ -505,14 +700,40 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
     return L;
 }
 
-template <int N, int JP, typename T>
+template <int N, int JP, typename T, bool EXACT>
 void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
                             T eta, hipStream_t st) {
-    if (count <= 0) return;
     LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
-    const size_t smem = ((size_t)N * s.H * (JP + 1) + (size_t)kTile * JP * N + 2) * sizeof(T);
-    hipLaunchKernelGGL((k_lf_tensor<N, JP, T>), dim3((unsigned)count), dim3(kTile), smem, st, A, Gp, L, eta,
-                       (T)(N + 1));
+    LFMatArgs<T> Y{};
+    Y.M = s.M;
+    Y.lambda_m = (T)s.lambda_m;
+    int64_t blocks = count;
+    for (int m = 0; m < s.M; ++m) {
+        Y.row[m] = s.b.y_row[m];
+        Y.col[m] = s.b.y_col[m];
+        Y.val[m] = (const T *)s.b.y_val[m];
+        Y.nnz[m] = s.y_nnz[m];
+        Y.Uc[m] = (T *)s.b.U[s.mat_mode[m]];
+        Y.V[m] = (T *)s.b.V[m];
+        Y.J[m] = s.mat_J[m];
+        Y.cntV[m] = s.cntV[m];
+        Y.n_tiles[m] = s.m_tiles[m];
+        Y.tile_base[m] = s.m_base[m];
+        Y.n_blocks[m] = s.m_count[m];
+        Y.pa[m] = s.mpa[m];
+        Y.pb[m] = s.mpb[m];
+        Y.tab_out[m] = (T *)s.tab_m[m];
+        Y.meta_slot[m] = s.meta_mslot[m];
+        Y.meta_rv[m] = (const T *)s.meta_rv[m];
+        Y.gu[m] = s.mat_mode[m];
+        Y.gv[m] = N + m;
+        blocks += s.m_count[m];
+    }
+    if (blocks <= 0) return;
+    const size_t smem = std::max((size_t)N * s.H * (JP + 1) + (size_t)kTile * JP * N + 2,
+                                 (size_t)2 * s.H * (JP + 1)) * sizeof(T);
+    hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
+                       count, eta, (T)(N + 1));
 }
 
 inline uint64_t splitmix64(uint64_t &x) {
@@ -552,21 +773,16 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
         const int64_t t0 = s.t_tiles * r / R, t1 = s.t_tiles * (r + 1) / R;
         s.pa = tpa;
         s.pb = tpb;
-        tensor_round(t0, t1 - t0, eta, st);
         s.apply.nwg_t = t1 - t0;
         for (int m = 0; m < M; ++m) {
             const int64_t m0 = s.m_tiles[m] * r / R, m1 = s.m_tiles[m] * (r + 1) / R;
-            s.apply.nwg_m[m] = std::max<int64_t>(0, m1 - m0);
-            if (m1 <= m0) continue;
-            s.pa = mpa[m];
-            s.pb = mpb[m];
-            LFArgs<T> L = lf_args<T>(s, s.m_tiles[m], m0, (T *)s.tab_m[m], nullptr);
-            const int c = d.mat_mode[m];
-            const size_t smem = (size_t)2 * s.H * (s.JP + 1) * sizeof(T);
-            hipLaunchKernelGGL(k_lf_matrix<T>, dim3((unsigned)(m1 - m0)), dim3(kTile), smem, st, s.b.y_row[m],
-                               s.b.y_col[m], (const T *)s.b.y_val[m], s.y_nnz[m], (T *)s.b.U[c], (T *)s.b.V[m],
-                               J[c], s.cntV[m], (T)d.lambda_m, (T)d.lambda_reg, L, c, N + m, (T)eta, kappa);
+            s.m_base[m] = m0;
+            s.m_count[m] = std::max<int64_t>(0, m1 - m0);
+            s.mpa[m] = mpa[m];
+            s.mpb[m] = mpb[m];
+            s.apply.nwg_m[m] = s.m_count[m];
         }
+        tensor_round(t0, t1 - t0, eta, st);  // tensor and matrix tiles, one launch
         if (t1 > t0)
             hipLaunchKernelGGL(k_lf_core_sum<T>, dim3((unsigned)((s.KP + 2 + 15) / 16)), dim3(256), 0, st,
                                (const T *)s.core_t, t1 - t0, s.KP + 2, (T *)s.core_sum);

@@ -62,6 +62,7 @@ struct KernelSet {
 struct s3_plan {
     s3_desc d{};
     int N = 0, M = 0, JP = 0;
+    bool exact = false;  // every rank equals JP
     int64_t K = 1, KP = 1;
     size_t tsize = 4;  // sizeof compute type
     bool bound = false;
@@ -176,8 +177,12 @@ template <int N, int JP, typename T> struct Impl {
                            (const T *)p->Gp, (T *)out);
     }
     static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st) {
-        lockfree_tensor_launch<N, JP, T>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                         (const T *)p->Gp, first, count, (T)eta, st);
+        if (p->exact)
+            lockfree_tensor_launch<N, JP, T, true>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+                                                   (const T *)p->Gp, first, count, (T)eta, st);
+        else
+            lockfree_tensor_launch<N, JP, T, false>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+                                                    (const T *)p->Gp, first, count, (T)eta, st);
     }
 };
 
@@ -345,7 +350,7 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     if (d.n_mat < 0 || d.n_mat > S3_MAX_MATRICES) return S3_ERR_INVALID_ARG;
     if (d.dtype != S3_F64 && d.dtype != S3_F32 && d.dtype != S3_BF16) return S3_ERR_UNSUPPORTED;
     if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
-    if (d.batch < 1 || d.round_items < 1 || d.hot_rows < 0 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
+    if (d.batch < 1 || d.round_items < 1 || d.hot_rows < -1 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
     if (!(d.eta0 > 0) || !(d.mu >= 0) || !(d.lambda_reg >= 0) || !(d.lambda_m >= 0)) return S3_ERR_INVALID_ARG;
     int Jmax = 0;
     for (int n = 0; n < d.order; ++n) {
@@ -364,6 +369,8 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     p->M = d.n_mat;
     p->JP = JP;
     for (int n = 0; n < p->N; ++n) { p->K *= d.rank[n]; p->KP *= JP; }
+    p->exact = true;
+    for (int n = 0; n < p->N; ++n) p->exact = p->exact && d.rank[n] == JP;
     p->tsize = (d.dtype == S3_F64) ? 8 : 4;
     const bool ok = (d.dtype == S3_F64) ? pick_set<double>(p->N, JP, &p->ks) : pick_set<float>(p->N, JP, &p->ks);
     if (!ok) {
