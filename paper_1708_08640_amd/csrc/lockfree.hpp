@@ -20,10 +20,9 @@
 //          whole hot-row
 //          table and core partial to its own slot of a partials buffer
 //          (plain coalesced stores: no global atomics).
-//   k_lf_core_sum  sums the round's core partials in a fixed order.
-//   k_lf_apply  one workgroup per hot row (and per core chunk): sums the
-//          hot-row partials of every workgroup of the round in a fixed order
-//          and moves the row / the core once by the damped step
+//   k_lf_apply  one workgroup per hot row and one per 16 core elements:
+//          sums the round's partials of every workgroup in a fixed order and
+//          moves the row / the core once by the damped step
 //          -eta sum g / max(1, k eta sum L).
 // "Hot" rows are the H most frequent rows of each mode and of each coupled
 // factor.  The paper lets one worker own the core, which every entry
@@ -70,6 +69,32 @@ template <int JP, int TAIL> constexpr int lf_split() {
     return best;
 }
 
+// The hottest kRepSlots slots of every table (slots are numbered by
+// decreasing row frequency) accumulate into kRep replicas picked by lane, so
+// the dozen lanes of a wavefront that share the most frequent row do not
+// serialise on one LDS address; the replicas are folded into the table
+// before it is written out.
+constexpr int kRepSlots = 4;
+constexpr int kRep = 8;
+
+template <int JP, typename T> S3_DEV T *lf_acc(T *s_tab, T *s_rep, int H, int grp, int slot) {
+    return slot < kRepSlots
+               ? s_rep + (((size_t)grp * kRepSlots + slot) * kRep + (threadIdx.x & (kRep - 1))) * (JP + 1)
+               : s_tab + ((size_t)grp * H + slot) * (JP + 1);
+}
+
+// replicas -> table (between two barriers)
+template <int JP, typename T> S3_DEV void lf_fold(T *s_tab, const T *s_rep, int H, int groups) {
+    constexpr int W = JP + 1;
+    for (int i = threadIdx.x; i < groups * kRepSlots * W; i += kTile) {
+        const int k = i % W, gs = i / W, grp = gs / kRepSlots, slot = gs % kRepSlots;
+        T t = T(0);
+#pragma unroll
+        for (int r = 0; r < kRep; ++r) t += s_rep[((size_t)gs * kRep + r) * W + k];
+        s_tab[((size_t)grp * H + slot) * W + k] = t;
+    }
+}
+
 // ------------------------------------------------------------------ matrix
 
 // Coupled-matrix tiles of one round; they run in the same launch as the
@@ -100,7 +125,8 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
                            T *s_tab) {
     const int tid = threadIdx.x;
     const int tabn = 2 * L.H * (JP + 1);
-    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
+    T *s_rep = s_tab + tabn;  // [2][kRepSlots][kRep][JP + 1]
+    for (int i = tid; i < tabn + 2 * kRepSlots * kRep * (JP + 1); i += kTile) s_tab[i] = T(0);
     __syncthreads();
     const int64_t tile = lf_perm(Y.tile_base[m] + blk, Y.pa[m], Y.pb[m], Y.n_tiles[m]);
     const int64_t e = tile * kTile + tid;
@@ -126,7 +152,7 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
         const int su = (int)(int16_t)(ms & 0xffffu);
         const int sv = (int)(int16_t)(ms >> 16);
         if (su >= 0) {
-            T *t = s_tab + (size_t)su * (JP + 1);
+            T *t = lf_acc<JP>(s_tab, s_rep, L.H, 0, su);
 #pragma unroll
             for (int k = 0; k < JP; ++k) atomicAdd(&t[k], q * vr[k]);
             atomicAdd(&t[JP], Lu);
@@ -138,7 +164,7 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
                 if (EXACT || k < J) u[k] = ur[k] - step * q * vr[k];
         }
         if (sv >= 0) {
-            T *t = s_tab + ((size_t)L.H + sv) * (JP + 1);
+            T *t = lf_acc<JP>(s_tab, s_rep, L.H, 1, sv);
 #pragma unroll
             for (int k = 0; k < JP; ++k) atomicAdd(&t[k], fmaT(q, ur[k], rv * vr[k]));
             atomicAdd(&t[JP], Lv);
@@ -150,6 +176,8 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
                 if (EXACT || k < J) v[k] = vr[k] - step * fmaT(q, ur[k], rv * vr[k]);
         }
     }
+    __syncthreads();
+    lf_fold<JP>(s_tab, s_rep, L.H, 2);
     __syncthreads();
     T *tab = Y.tab_out[m] + (size_t)blk * tabn;
     for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
@@ -239,12 +267,13 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
         return;
     }
     T *s_tab = (T *)smem_raw;                         // [N][H][JP + 1]
-    T *s_q = s_tab + (size_t)N * L.H * (JP + 1);     // [kTile][JP]  q * u^(1)
+    T *s_rep = s_tab + (size_t)N * L.H * (JP + 1);   // [N][kRepSlots][kRep][JP + 1]
+    T *s_q = s_rep + (size_t)N * kRepSlots * kRep * (JP + 1);  // [kTile][JP]  q * u^(1)
     T *s_u = s_q + kTile * JP;                        // [kTile][N - 1][JP]
     T *s_misc = s_u + (size_t)kTile * (N - 1) * JP;   // [0] core curvature, [1] count
     const int tid = threadIdx.x;
     const int tabn = N * L.H * (JP + 1);
-    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
+    for (int i = tid; i < tabn + N * kRepSlots * kRep * (JP + 1); i += kTile) s_tab[i] = T(0);
     if (tid < 2) s_misc[tid] = T(0);
     __syncthreads();
 
@@ -277,7 +306,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
             const uint32_t half = (n < 2) ? ms.x : ms.y;
             const int slot = (int)(int16_t)((n & 1) ? (half >> 16) : (half & 0xffffu));
             if (slot >= 0) {
-                T *t = s_tab + ((size_t)n * L.H + slot) * (JP + 1);
+                T *t = lf_acc<JP>(s_tab, s_rep, L.H, n, slot);
 #pragma unroll
                 for (int k = 0; k < JP; ++k) atomicAdd(&t[k], fmaT(q, w[n][k], reg * u[n][k]));
                 atomicAdd(&t[JP], ell);
@@ -308,6 +337,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
             for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = T(0);
     }
     __syncthreads();
+    lf_fold<JP>(s_tab, s_rep, L.H, N);
     T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
     if constexpr (std::is_same<T, float>::value) {
         lf_core_tile_mfma<N, JP>(s_q, s_u, core);
@@ -341,6 +371,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
         core[KP + 1] = s_misc[1];
     }
     // the workgroup's hot-row table, written densely
+    __syncthreads();
     T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
     for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
 }
@@ -362,126 +393,130 @@ struct LFApplyArgs {
     const void *tab_m[kMaxM];               // matrix tables [nwg_m][2][H][JP+1]
     int64_t nwg_m[kMaxM];
     const void *core_t;                     // tensor core partials [nwg_t][KP+2]
-    const void *core_sum;                   // their sum over the round [KP+2]
+    int64_t KP;                             // padded core size JP^N
 };
 
 constexpr int kApplyThreads = 256;
 
-// fixed-order sum over the block of n values per thread (n <= 17): a
-// butterfly inside each wavefront, then the wavefronts in order
-template <typename T> S3_DEV void lf_block_sum(T *vals, int n, T *s_red) {
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    constexpr int NW = kApplyThreads / kWave;
-#pragma unroll
-    for (int k = 0; k < 17; ++k)
-        if (k < n) vals[k] = wave_sum(vals[k]);
-    if (lane == 0)
-        for (int k = 0; k < n; ++k) s_red[k * NW + wv] = vals[k];
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        T t = T(0);
-        for (int w = 0; w < NW; ++w) t += s_red[k * NW + w];
-        vals[k] = t;
-    }
-}
-
-// Fixed-order sum of the round's per-workgroup core partials (and their
-// curvature and entry count): 16 consecutive elements per block, 16
-// workgroup phases per element, four independent running sums per thread.
-template <typename T>
-__global__ __launch_bounds__(256) void k_lf_core_sum(const T *__restrict__ core_t, int64_t nwg, int64_t cs,
-                                                     T *__restrict__ core_sum) {
-    __shared__ T s_part[16][17];
-    const int el = threadIdx.x & 15, ph = threadIdx.x >> 4;
-    const int64_t j = (int64_t)blockIdx.x * 16 + el;
-    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-    if (j < cs) {
-        int64_t b = ph;
-        for (; b + 48 < nwg; b += 64) {
-            a0 += core_t[b * cs + j];
-            a1 += core_t[(b + 16) * cs + j];
-            a2 += core_t[(b + 32) * cs + j];
-            a3 += core_t[(b + 48) * cs + j];
-        }
-        for (; b < nwg; b += 16) a0 += core_t[b * cs + j];
-    }
-    s_part[ph][el] = (a0 + a1) + (a2 + a3);
-    __syncthreads();
-    if (ph == 0 && j < cs) {
-        T t = T(0);
-        for (int q = 0; q < 16; ++q) t += s_part[q][el];
-        core_sum[j] = t;
-    }
-}
-
-// blocks [0, groups * H): one hot row each; blocks after: core chunks of
-// kApplyThreads elements
+// blocks [0, groups * H): one hot row each; blocks after: 16 core elements
+// each (in the zero-padded JP^N layout)
 template <int N, typename T>
 __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H, int JP, T *__restrict__ G,
                                                             T *__restrict__ Gp, int J0, int J1, int J2, int J3,
                                                             T reg_core, T eta, T kappa) {
-    __shared__ T s_red[17 * (kApplyThreads / kWave)];
+    constexpr int NW = kApplyThreads / kWave;
+    __shared__ T s_red[32 * NW];
     const int tid = threadIdx.x;
     const int nrowblk = a.groups * H;
     if ((int)blockIdx.x < nrowblk) {
         const int g = blockIdx.x / H, slot = blockIdx.x % H;
         const int row = a.hot_row[g][slot];
         if (row < 0) return;  // uniform over the block
-        T acc[17];
+        // lane groups of KW lanes read one workgroup's JP + 1 contiguous
+        // values each (lane k: element k); NS groups stride over workgroups
+        const int W = JP + 1;
+        const int lk = (W <= 16) ? 4 : 5, KW = 1 << lk, NS = kApplyThreads >> lk;
+        const int k = tid & (KW - 1), sub = tid >> lk;
+        // eight loads in flight per lane, eight running sums
+        constexpr int UN = 8;
+        T acc8[UN];
 #pragma unroll
-        for (int k = 0; k < 17; ++k) acc[k] = T(0);
-        const size_t W = (size_t)JP + 1;
-        if (g < N) {
-            const T *src = (const T *)a.tab_t + ((size_t)g * H + slot) * W;
-            const size_t stride = (size_t)N * H * W;
-            for (int64_t b = tid; b < a.nwg_t; b += kApplyThreads)
-                for (int k = 0; k <= JP; ++k) acc[k] += src[b * stride + k];
+        for (int i = 0; i < UN; ++i) acc8[i] = T(0);
+        auto sweep = [&](const T *src, size_t stride, int64_t nwg) {
+            int64_t b = sub;
+            for (; b + (UN - 1) * NS < nwg; b += UN * NS) {
+                T v[UN];
+#pragma unroll
+                for (int i = 0; i < UN; ++i) v[i] = src[(b + i * NS) * stride + k];
+#pragma unroll
+                for (int i = 0; i < UN; ++i) acc8[i] += v[i];
+            }
+            for (int i = 0; b < nwg; b += NS, ++i) acc8[i & (UN - 1)] += src[b * stride + k];
+        };
+        if (k < W) {
+            if (g < N) sweep((const T *)a.tab_t + ((size_t)g * H + slot) * W, (size_t)N * H * W, a.nwg_t);
+            for (int m = 0; m < a.M; ++m) {
+                int side = -1;
+                if (g < N && a.mat_mode[m] == g) side = 0;
+                if (g == N + m) side = 1;
+                if (side >= 0)
+                    sweep((const T *)a.tab_m[m] + ((size_t)side * H + slot) * W, (size_t)2 * H * W, a.nwg_m[m]);
+            }
         }
-        for (int m = 0; m < a.M; ++m) {
-            int side = -1;
-            if (g < N && a.mat_mode[m] == g) side = 0;
-            if (g == N + m) side = 1;
-            if (side < 0) continue;
-            const T *src = (const T *)a.tab_m[m] + ((size_t)side * H + slot) * W;
-            const size_t stride = (size_t)2 * H * W;
-            for (int64_t b = tid; b < a.nwg_m[m]; b += kApplyThreads)
-                for (int k = 0; k <= JP; ++k) acc[k] += src[b * stride + k];
+        T acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+        // lanes of one wavefront holding the same element
+        for (int off = KW; off < kWave; off <<= 1) acc += __shfl_xor(acc, off, kWave);
+        const int lane = tid & (kWave - 1), wv = tid / kWave;
+        if (lane < KW) s_red[wv * 32 + lane] = acc;
+        __syncthreads();
+        if (tid >= a.J[g]) return;
+        T gk = T(0), Lsum = T(0);
+        for (int w = 0; w < NW; ++w) {
+            gk += s_red[w * 32 + tid];
+            Lsum += s_red[w * 32 + JP];
         }
-        lf_block_sum<T>(acc, JP + 1, s_red);
-        const T Lsum = acc[JP];
-        if (Lsum != T(0) && tid < a.J[g]) {
+        if (Lsum != T(0)) {
             const T d = kappa * eta * Lsum;
             const T step = eta / (d > T(1) ? d : T(1));
             T *p = (T *)a.P[g] + (int64_t)row * a.J[g];
-            T gk = T(0);
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k == tid) gk = acc[k];
             p[tid] -= step * gk;
         }
         return;
     }
-    // core (the round's sums come from k_lf_core_sum)
+    // core: lane el of phase ph sums element el of this block over the
+    // workgroups ph, ph + 16, ...; the phases are then added in order.  Every
+    // lane also sums the two trailing entries (core curvature, entry count).
+    __shared__ T s_part[3][16][17];
+    const int el = tid & 15, ph = tid >> 4;
+    const int64_t cs = a.KP + 2;
+    const int64_t jp = (int64_t)(blockIdx.x - nrowblk) * 16 + el;
+    const T *ct = (const T *)a.core_t;
+    T e4[4] = {T(0), T(0), T(0), T(0)}, l4[4] = {T(0), T(0), T(0), T(0)}, c4[4] = {T(0), T(0), T(0), T(0)};
+    const int64_t jr = jp < a.KP ? jp : a.KP;  // lanes past the end re-read a valid column
+    int64_t b = ph;
+    for (; b + 48 < a.nwg_t; b += 64) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T *row = ct + (b + 16 * i) * cs;
+            e4[i] += row[jr];
+            l4[i] += row[a.KP];
+            c4[i] += row[a.KP + 1];
+        }
+    }
+    for (; b < a.nwg_t; b += 16) {
+        const T *row = ct + b * cs;
+        e4[0] += row[jr];
+        l4[0] += row[a.KP];
+        c4[0] += row[a.KP + 1];
+    }
+    s_part[0][ph][el] = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+    s_part[1][ph][el] = (l4[0] + l4[1]) + (l4[2] + l4[3]);
+    s_part[2][ph][el] = (c4[0] + c4[1]) + (c4[2] + c4[3]);
+    __syncthreads();
+    if (ph != 0 || jp >= a.KP) return;
+    T gsum = T(0), LG = T(0), cnt = T(0);
+    for (int q = 0; q < 16; ++q) {
+        gsum += s_part[0][q][el];
+        LG += s_part[1][q][el];
+        cnt += s_part[2][q][el];
+    }
+    if (cnt == T(0)) return;
+    // padded index -> core index (skip the zero padding)
     const int Js[4] = {J0, J1, J2, J3};
-    int K = 1, KP = 1;
-    for (int n = 0; n < N; ++n) { K *= Js[n]; KP *= JP; }
-    const int j = (blockIdx.x - nrowblk) * kApplyThreads + tid;
-    const T *cs = (const T *)a.core_sum;
-    const T LG = cs[KP], cnt = cs[KP + 1];
-    if (j >= K || cnt == T(0)) return;
-    int rem = j, pj = 0, mul = 1;
+    int64_t rem = jp, j = 0, mul = 1;
     for (int n = N - 1; n >= 0; --n) {
-        const int jn = rem % Js[n];
-        rem /= Js[n];
-        pj += jn * mul;
-        mul *= JP;
+        const int jn = (int)(rem % JP);
+        rem /= JP;
+        if (jn >= Js[n]) return;
+        j += jn * mul;
+        mul *= Js[n];
     }
     const T Lsum = LG + cnt * reg_core;
     const T d = kappa * eta * Lsum;
     const T step = eta / (d > T(1) ? d : T(1));
-    const T gnew = G[j] - step * (cs[pj] + cnt * reg_core * G[j]);
+    const T gnew = G[j] - step * (gsum + cnt * reg_core * G[j]);
     G[j] = gnew;
-    Gp[pj] = gnew;
+    Gp[jp] = gnew;
 }
 
 // ---------------------------------------------------------------- metadata
@@ -533,7 +568,7 @@ struct LockFreeState {
     int32_t *hot_slot[kMaxN + kMaxM] = {};
     int32_t *hot_row[kMaxN + kMaxM] = {};
     int64_t rows[kMaxN + kMaxM] = {};
-    void *tab_t = nullptr, *core_t = nullptr, *core_sum = nullptr;
+    void *tab_t = nullptr, *core_t = nullptr;
     uint2 *meta_slot = nullptr;
     void *meta_reg = nullptr;
     uint32_t *meta_mslot[kMaxM] = {};
@@ -560,7 +595,7 @@ constexpr size_t kLfLdsBudget = 64 * 1024;
 // the largest that lets the tensor kernel's LDS fit the budget (0: none
 // fits).  A negative request keeps a minimal table but marks no row hot.
 inline int lf_hot_rows(int N, int JP, size_t tsize, int requested) {
-    const size_t staging = ((size_t)kTile * N * JP + 2) * tsize;
+    const size_t staging = ((size_t)kTile * N * JP + 2 + (size_t)N * kRepSlots * kRep * (JP + 1)) * tsize;
     for (int H = 256; H >= 16; H /= 2)
         if ((requested <= 0 || H <= requested) && staging + (size_t)N * H * (JP + 1) * tsize <= kLfLdsBudget)
             return requested < 0 ? std::min(H, 16) : H;
@@ -602,7 +637,6 @@ void lockfree_layout(LockFreeState &s, C &c, int N, int M, const s3_desc &d, int
         s.meta_rv[m] = c.template take<T>((size_t)std::max<int64_t>(y_nnz[m], 1));
     }
     s.core_t = c.template take<T>((size_t)s.max_t_wg * (KP + 2));
-    s.core_sum = c.template take<T>((size_t)KP + 2);
 }
 
 // pick the H most frequent rows of every group (host side, from the counts)
@@ -668,7 +702,7 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
     }
     s.apply.tab_t = s.tab_t;
     s.apply.core_t = s.core_t;
-    s.apply.core_sum = s.core_sum;
+    s.apply.KP = s.KP;
     // per-entry metadata streams
     LFMetaSrc src{};
     for (int g = 0; g < N + M; ++g) src.hot_slot[g] = s.hot_slot[g];
@@ -730,8 +764,9 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
         blocks += s.m_count[m];
     }
     if (blocks <= 0) return;
-    const size_t smem = std::max((size_t)N * s.H * (JP + 1) + (size_t)kTile * JP * N + 2,
-                                 (size_t)2 * s.H * (JP + 1)) * sizeof(T);
+    const size_t rep = (size_t)kRepSlots * kRep * (JP + 1);
+    const size_t smem = std::max((size_t)N * (s.H * (JP + 1) + rep) + (size_t)kTile * JP * N + 2,
+                                 (size_t)2 * (s.H * (JP + 1) + rep)) * sizeof(T);
     hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
                        count, eta, (T)(N + 1));
 }
@@ -767,8 +802,6 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
     const T kappa = (T)(N + 1);
     const T reg_core = (T)(d.lambda_reg / (double)s.nX);
     const int *J = d.rank;
-    int64_t K = 1;
-    for (int n = 0; n < N; ++n) K *= J[n];
     for (int64_t r = 0; r < R; ++r) {
         const int64_t t0 = s.t_tiles * r / R, t1 = s.t_tiles * (r + 1) / R;
         s.pa = tpa;
@@ -783,12 +816,7 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
             s.apply.nwg_m[m] = s.m_count[m];
         }
         tensor_round(t0, t1 - t0, eta, st);  // tensor and matrix tiles, one launch
-        if (t1 > t0)
-            hipLaunchKernelGGL(k_lf_core_sum<T>, dim3((unsigned)((s.KP + 2 + 15) / 16)), dim3(256), 0, st,
-                               (const T *)s.core_t, t1 - t0, s.KP + 2, (T *)s.core_sum);
-        else
-            hipLaunchKernelGGL(k_fill<T>, dim3(4), dim3(256), 0, st, (T *)s.core_sum, s.KP + 2, T(0));
-        const int64_t blocks = (int64_t)(N + M) * s.H + (K + kApplyThreads - 1) / kApplyThreads;
+        const int64_t blocks = (int64_t)(N + M) * s.H + (s.KP + 15) / 16;
         auto kern = (N == 3) ? k_lf_apply<3, T> : k_lf_apply<4, T>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kApplyThreads), 0, st, s.apply, s.H, s.JP,
                            (T *)s.b.G, Gp, J[0], J[1], J[2], N > 3 ? J[3] : 1, reg_core, (T)eta, kappa);
