@@ -45,7 +45,9 @@ constexpr int kTile = 256;
 
 template <typename T> struct LFArgs {
     const int32_t *hot_slot[kMaxN + kMaxM];  // row -> slot in [0, H) or -1
-    const uint2 *meta_slot;  // per tensor entry: its rows' hot slots, int16 each (-1: cold)
+    const uint2 *meta_slot;  // per tensor entry: sorted hot position per mode, int16 each (-1: cold)
+    const uint32_t *chunks;  // [tile][N][kTile] chunk descriptors
+    const int32_t *nchunks;  // [tile][N]
     const T *meta_reg;       // per tensor entry and mode: lambda_reg / |Omega^{n,i_n}|, [N][nnz]
     T *tab_out;        // per-workgroup hot tables: [wg][groups][H][JP + 1]
     T *core_out;       // per-workgroup core partials: [wg][KP + 2] (tensor only)
@@ -69,30 +71,105 @@ template <int JP, int TAIL> constexpr int lf_split() {
     return best;
 }
 
-// The hottest kRepSlots slots of every table (slots are numbered by
-// decreasing row frequency) accumulate into kRep replicas picked by lane, so
-// the dozen lanes of a wavefront that share the most frequent row do not
-// serialise on one LDS address; the replicas are folded into the table
-// before it is written out.
-constexpr int kRepSlots = 4;
-constexpr int kRep = 8;
+// Hot-row contributions without atomics.  At bind time the hot entries of
+// every 256-entry tile are sorted by slot, per group (tensor mode, or u / V
+// side of a matrix); each entry keeps its position in that order and the
+// sorted run is cut into chunks of at most 16 entries of one slot.  In a
+// round an entry writes its gradient row (and curvature) to its position in
+// LDS with plain stores; one work item per (chunk, element) then sums the
+// chunk and stores it in the slot's table row (an atomic add only where a
+// slot's run spans several chunks).  Chunk descriptor: slot (bits 0-7),
+// first position (8-15), length - 1 (16-19), whole run (20).
+constexpr int kRun = 16;
 
-template <int JP, typename T> S3_DEV T *lf_acc(T *s_tab, T *s_rep, int H, int grp, int slot) {
-    return slot < kRepSlots
-               ? s_rep + (((size_t)grp * kRepSlots + slot) * kRep + (threadIdx.x & (kRep - 1))) * (JP + 1)
-               : s_tab + ((size_t)grp * H + slot) * (JP + 1);
+// per-entry packed int16 fields: slot (at bind) / position (after), -1 = cold
+S3_DEV int lf_field(uint2 m, int g) {
+    const uint32_t h = g < 2 ? m.x : m.y;
+    return (int)(int16_t)((g & 1) ? (h >> 16) : (h & 0xffffu));
+}
+S3_DEV int lf_field(uint32_t m, int g) { return (int)(int16_t)((g & 1) ? (m >> 16) : (m & 0xffffu)); }
+S3_DEV uint32_t lf_put(uint32_t h, int g, int v) {
+    const uint32_t f = (uint32_t)(uint16_t)(int16_t)v;
+    return (g & 1) ? ((h & 0xffffu) | (f << 16)) : ((h & 0xffff0000u) | f);
+}
+S3_DEV void lf_set(uint2 &m, int g, int v) {
+    if (g < 2) m.x = lf_put(m.x, g, v); else m.y = lf_put(m.y, g, v);
+}
+S3_DEV void lf_set(uint32_t &m, int g, int v) { m = lf_put(m, g, v); }
+template <typename P> S3_DEV P lf_cold();
+template <> S3_DEV uint2 lf_cold<uint2>() { return make_uint2(0xffffffffu, 0xffffffffu); }
+template <> S3_DEV uint32_t lf_cold<uint32_t>() { return 0xffffffffu; }
+
+// G groups of one tile: s_stage [G][JP + 1][kTile] (sorted positions),
+// s_tab [G][H][JP + 1] (zeroed); between two barriers
+template <int JP, int G, typename T>
+S3_DEV void lf_chunk_pass(const T *s_stage, T *s_tab, const uint32_t *chunks, const int32_t *nchunks, int H) {
+    constexpr int W = JP + 1;
+    int base[G + 1];
+    base[0] = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) base[g + 1] = base[g] + nchunks[g] * W;
+    for (int item = threadIdx.x; item < base[G]; item += kTile) {
+        int g = 0;
+#pragma unroll
+        for (int h = 1; h < G; ++h) g += item >= base[h];
+        const int c = (item - base[g]) / W, k = (item - base[g]) - c * W;
+        const uint32_t d = chunks[(size_t)g * kTile + c];
+        const int slot = d & 0xff, start = (d >> 8) & 0xff, len = ((d >> 16) & 0xf) + 1;
+        const T *src = s_stage + ((size_t)g * W + k) * kTile + start;
+        T sum = T(0);
+#pragma unroll
+        for (int j = 0; j < kRun; ++j)
+            if (j < len) sum += src[j];
+        T *dst = s_tab + ((size_t)g * H + slot) * W + k;
+        if ((d >> 20) & 1) *dst = sum;
+        else atomicAdd(dst, sum);
+    }
 }
 
-// replicas -> table (between two barriers)
-template <int JP, typename T> S3_DEV void lf_fold(T *s_tab, const T *s_rep, int H, int groups) {
-    constexpr int W = JP + 1;
-    for (int i = threadIdx.x; i < groups * kRepSlots * W; i += kTile) {
-        const int k = i % W, gs = i / W, grp = gs / kRepSlots, slot = gs % kRepSlots;
-        T t = T(0);
-#pragma unroll
-        for (int r = 0; r < kRep; ++r) t += s_rep[((size_t)gs * kRep + r) * W + k];
-        s_tab[((size_t)grp * H + slot) * W + k] = t;
+// bind time: slots -> positions and chunk descriptors, one workgroup per tile
+template <typename P, int G>
+__global__ __launch_bounds__(kTile) void k_lf_chunks(P *__restrict__ meta, int64_t nnz, uint32_t *__restrict__ chunks,
+                                                     int32_t *__restrict__ nchunks) {
+    __shared__ int s_slot[kTile];
+    __shared__ int s_wtot[kTile / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t tile = blockIdx.x;
+    const int64_t e = tile * kTile + tid;
+    P m = (e < nnz) ? meta[e] : lf_cold<P>();
+    for (int g = 0; g < G; ++g) {
+        const int slot = lf_field(m, g);
+        s_slot[tid] = slot;
+        __syncthreads();
+        int pos = 0, seg0 = 0, seglen = 0;
+        if (slot >= 0)
+            for (int l = 0; l < kTile; ++l) {
+                const int s2 = s_slot[l];
+                const bool lower = s2 >= 0 && s2 < slot;
+                seg0 += lower;
+                seglen += s2 == slot;
+                pos += lower || (s2 == slot && l < tid);
+            }
+        const bool head = slot >= 0 && (pos - seg0) % kRun == 0;
+        const uint64_t bal = __ballot(head);
+        if (lane == 0) s_wtot[wv] = __popcll(bal);
+        __syncthreads();
+        int cidx = __popcll(bal & ((1ull << lane) - 1)), total = 0;
+        for (int w = 0; w < kTile / kWave; ++w) {
+            if (w < wv) cidx += s_wtot[w];
+            total += s_wtot[w];
+        }
+        if (head) {
+            const int len = min(kRun, seg0 + seglen - pos);
+            chunks[((size_t)tile * G + g) * kTile + cidx] = (uint32_t)slot | ((uint32_t)pos << 8) |
+                                                            ((uint32_t)(len - 1) << 16) |
+                                                            ((seglen <= kRun ? 1u : 0u) << 20);
+        }
+        if (tid == 0) nchunks[tile * G + g] = total;
+        lf_set(m, g, slot >= 0 ? pos : -1);
+        __syncthreads();
     }
+    if (e < nnz) meta[e] = m;
 }
 
 // ------------------------------------------------------------------ matrix
@@ -113,7 +190,9 @@ template <typename T> struct LFMatArgs {
     int64_t n_blocks[kMaxM];  // tiles of this round
     uint64_t pa[kMaxM], pb[kMaxM];
     T *tab_out[kMaxM];        // [wg][2][H][JP + 1]
-    const uint32_t *meta_slot[kMaxM];  // per entry: u-row and V-row hot slots (int16 each, -1 cold)
+    const uint32_t *meta_slot[kMaxM];  // per entry: u-side and V-side sorted hot positions (int16, -1 cold)
+    const uint32_t *chunks[kMaxM];     // [tile][2][kTile]
+    const int32_t *nchunks[kMaxM];     // [tile][2]
     const T *meta_rv[kMaxM];           // per entry: lambda_m lambda_reg / |Omega_Y^{2,k}|
     int gu[kMaxM], gv[kMaxM];
     int M;
@@ -123,11 +202,11 @@ template <typename T> struct LFMatArgs {
 template <int JP, typename T, bool EXACT>
 S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFArgs<T> &L, T eta, T kappa,
                            T *s_tab) {
+    constexpr int W = JP + 1;
     const int tid = threadIdx.x;
-    const int tabn = 2 * L.H * (JP + 1);
-    T *s_rep = s_tab + tabn;  // [2][kRepSlots][kRep][JP + 1]
-    for (int i = tid; i < tabn + 2 * kRepSlots * kRep * (JP + 1); i += kTile) s_tab[i] = T(0);
-    __syncthreads();
+    const int tabn = 2 * L.H * W;
+    T *s_stage = s_tab + tabn;  // [2][W][kTile]
+    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
     const int64_t tile = lf_perm(Y.tile_base[m] + blk, Y.pa[m], Y.pb[m], Y.n_tiles[m]);
     const int64_t e = tile * kTile + tid;
     const int J = EXACT ? JP : Y.J[m];
@@ -149,13 +228,12 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
         const T q = -Y.lambda_m * (Y.val[m][e] - yh);
         const T rv = Y.meta_rv[m][e];
         const T Lu = Y.lambda_m * vv, Lv = fmaT(Y.lambda_m, uu, rv);
-        const int su = (int)(int16_t)(ms & 0xffffu);
-        const int sv = (int)(int16_t)(ms >> 16);
-        if (su >= 0) {
-            T *t = lf_acc<JP>(s_tab, s_rep, L.H, 0, su);
+        const int pu = lf_field(ms, 0), pv = lf_field(ms, 1);
+        if (pu >= 0) {
+            T *t = s_stage + pu;
 #pragma unroll
-            for (int k = 0; k < JP; ++k) atomicAdd(&t[k], q * vr[k]);
-            atomicAdd(&t[JP], Lu);
+            for (int k = 0; k < JP; ++k) t[k * kTile] = q * vr[k];
+            t[JP * kTile] = Lu;
         } else {
             const T d = kappa * eta * Lu;
             const T step = eta / (d > T(1) ? d : T(1));
@@ -163,11 +241,11 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
             for (int k = 0; k < JP; ++k)
                 if (EXACT || k < J) u[k] = ur[k] - step * q * vr[k];
         }
-        if (sv >= 0) {
-            T *t = lf_acc<JP>(s_tab, s_rep, L.H, 1, sv);
+        if (pv >= 0) {
+            T *t = s_stage + W * kTile + pv;
 #pragma unroll
-            for (int k = 0; k < JP; ++k) atomicAdd(&t[k], fmaT(q, ur[k], rv * vr[k]));
-            atomicAdd(&t[JP], Lv);
+            for (int k = 0; k < JP; ++k) t[k * kTile] = fmaT(q, ur[k], rv * vr[k]);
+            t[JP * kTile] = Lv;
         } else {
             const T d = kappa * eta * Lv;
             const T step = eta / (d > T(1) ? d : T(1));
@@ -177,7 +255,7 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
         }
     }
     __syncthreads();
-    lf_fold<JP>(s_tab, s_rep, L.H, 2);
+    lf_chunk_pass<JP, 2>(s_stage, s_tab, Y.chunks[m] + (size_t)tile * 2 * kTile, Y.nchunks[m] + tile * 2, L.H);
     __syncthreads();
     T *tab = Y.tab_out[m] + (size_t)blk * tabn;
     for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
@@ -266,21 +344,24 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
         }
         return;
     }
-    T *s_tab = (T *)smem_raw;                         // [N][H][JP + 1]
-    T *s_rep = s_tab + (size_t)N * L.H * (JP + 1);   // [N][kRepSlots][kRep][JP + 1]
-    T *s_q = s_rep + (size_t)N * kRepSlots * kRep * (JP + 1);  // [kTile][JP]  q * u^(1)
+    constexpr int W = JP + 1;
+    constexpr int NWV = kTile / kWave;
+    T *s_tab = (T *)smem_raw;                         // [N][H][W]
+    T *s_misc = s_tab + (size_t)N * L.H * W;          // per wavefront: core curvature, entry count
+    T *s_stage = s_misc + 2 * NWV;                    // [N][W][kTile] sorted hot rows, then:
+    T *s_q = s_stage;                                 // [kTile][JP]  q * u^(1)
     T *s_u = s_q + kTile * JP;                        // [kTile][N - 1][JP]
-    T *s_misc = s_u + (size_t)kTile * (N - 1) * JP;   // [0] core curvature, [1] count
     const int tid = threadIdx.x;
-    const int tabn = N * L.H * (JP + 1);
-    for (int i = tid; i < tabn + N * kRepSlots * kRep * (JP + 1); i += kTile) s_tab[i] = T(0);
-    if (tid < 2) s_misc[tid] = T(0);
-    __syncthreads();
+    const int tabn = N * L.H * W;
+    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
 
     const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
     const int64_t e = tile * kTile + tid;
-    if (e < A.nnz) {
-        T u[N][JP], w[N][JP];
+    const bool live = e < A.nnz;
+    T u[N][JP];
+    T q = T(0), LG = T(0);
+    if (live) {
+        T w[N][JP];
         int32_t rows[N];
         load_rows<N, JP, T, EXACT>(A, e, u, rows);
         const T xv = A.val[e];
@@ -290,8 +371,8 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
         for (int n = 0; n < N; ++n) regs[n] = L.meta_reg[(int64_t)n * A.nnz + e];
         T xhat;
         contract<N, JP, T>(Gp, u, w, xhat);
-        const T q = -(xv - xhat);
-        T LG = T(1);
+        q = -(xv - xhat);
+        LG = T(1);
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const T reg = regs[n];
@@ -303,13 +384,12 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
             }
             LG *= uu;
             const T ell = ww + reg;
-            const uint32_t half = (n < 2) ? ms.x : ms.y;
-            const int slot = (int)(int16_t)((n & 1) ? (half >> 16) : (half & 0xffffu));
-            if (slot >= 0) {
-                T *t = lf_acc<JP>(s_tab, s_rep, L.H, n, slot);
+            const int pos = lf_field(ms, n);
+            if (pos >= 0) {
+                T *t = s_stage + (size_t)n * W * kTile + pos;
 #pragma unroll
-                for (int k = 0; k < JP; ++k) atomicAdd(&t[k], fmaT(q, w[n][k], reg * u[n][k]));
-                atomicAdd(&t[JP], ell);
+                for (int k = 0; k < JP; ++k) t[k * kTile] = fmaT(q, w[n][k], reg * u[n][k]);
+                t[JP * kTile] = ell;
             } else {
                 const T d = kappa * eta * ell;
                 const T step = eta / (d > T(1) ? d : T(1));
@@ -319,15 +399,26 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
                     if (EXACT || k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
             }
         }
-        // stage the core-gradient operands
+    }
+    {
+        const T lg = wave_sum(LG);
+        const uint64_t bal = __ballot(live);
+        if ((tid & (kWave - 1)) == 0) {
+            s_misc[2 * (tid / kWave)] = lg;
+            s_misc[2 * (tid / kWave) + 1] = (T)__popcll(bal);
+        }
+    }
+    __syncthreads();
+    lf_chunk_pass<JP, N>(s_stage, s_tab, L.chunks + (size_t)tile * N * kTile, L.nchunks + tile * N, L.H);
+    __syncthreads();
+    // stage the core-gradient operands (over the sorted rows, now consumed)
+    if (live) {
 #pragma unroll
         for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
 #pragma unroll
         for (int n = 1; n < N; ++n)
 #pragma unroll
             for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = u[n][k];
-        atomicAdd(&s_misc[0], LG);
-        atomicAdd(&s_misc[1], T(1));
     } else {
 #pragma unroll
         for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = T(0);
@@ -337,7 +428,6 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
             for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = T(0);
     }
     __syncthreads();
-    lf_fold<JP>(s_tab, s_rep, L.H, N);
     T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
     if constexpr (std::is_same<T, float>::value) {
         lf_core_tile_mfma<N, JP>(s_q, s_u, core);
@@ -367,8 +457,13 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
         }
     }
     if (tid == 0) {
-        core[KP] = s_misc[0];
-        core[KP + 1] = s_misc[1];
+        T lg = T(0), cnt = T(0);
+        for (int w = 0; w < NWV; ++w) {
+            lg += s_misc[2 * w];
+            cnt += s_misc[2 * w + 1];
+        }
+        core[KP] = lg;
+        core[KP + 1] = cnt;
     }
     // the workgroup's hot-row table, written densely
     __syncthreads();
@@ -570,6 +665,10 @@ struct LockFreeState {
     int64_t rows[kMaxN + kMaxM] = {};
     void *tab_t = nullptr, *core_t = nullptr;
     uint2 *meta_slot = nullptr;
+    uint32_t *t_chunks = nullptr;
+    int32_t *t_nchunks = nullptr;
+    uint32_t *m_chunks[kMaxM] = {};
+    int32_t *m_nchunks[kMaxM] = {};
     void *meta_reg = nullptr;
     uint32_t *meta_mslot[kMaxM] = {};
     void *meta_rv[kMaxM] = {};
@@ -595,7 +694,7 @@ constexpr size_t kLfLdsBudget = 64 * 1024;
 // the largest that lets the tensor kernel's LDS fit the budget (0: none
 // fits).  A negative request keeps a minimal table but marks no row hot.
 inline int lf_hot_rows(int N, int JP, size_t tsize, int requested) {
-    const size_t staging = ((size_t)kTile * N * JP + 2 + (size_t)N * kRepSlots * kRep * (JP + 1)) * tsize;
+    const size_t staging = (std::max((size_t)kTile * N * (JP + 1), (size_t)kTile * N * JP) + 2 * (kTile / kWave)) * tsize;
     for (int H = 256; H >= 16; H /= 2)
         if ((requested <= 0 || H <= requested) && staging + (size_t)N * H * (JP + 1) * tsize <= kLfLdsBudget)
             return requested < 0 ? std::min(H, 16) : H;
@@ -632,9 +731,14 @@ void lockfree_layout(LockFreeState &s, C &c, int N, int M, const s3_desc &d, int
     s.tab_t = c.template take<T>((size_t)s.max_t_wg * N * H * (JP + 1));
     s.meta_slot = c.template take<uint2>((size_t)x_nnz);
     s.meta_reg = c.template take<T>((size_t)x_nnz * N);
+    s.t_chunks = c.template take<uint32_t>((size_t)tt * N * kTile);
+    s.t_nchunks = c.template take<int32_t>((size_t)tt * N);
     for (int m = 0; m < M; ++m) {
         s.meta_mslot[m] = c.template take<uint32_t>((size_t)std::max<int64_t>(y_nnz[m], 1));
         s.meta_rv[m] = c.template take<T>((size_t)std::max<int64_t>(y_nnz[m], 1));
+        const int64_t mt = (y_nnz[m] + kTile - 1) / kTile;
+        s.m_chunks[m] = c.template take<uint32_t>((size_t)mt * 2 * kTile);
+        s.m_nchunks[m] = c.template take<int32_t>((size_t)mt * 2);
     }
     s.core_t = c.template take<T>((size_t)s.max_t_wg * (KP + 2));
 }
@@ -714,6 +818,20 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
             hipLaunchKernelGGL(k_lf_meta_matrix<T>, dim3(4096), dim3(256), 0, st, buf->y_row[m], buf->y_col[m],
                                y_nnz[m], s.hot_slot[d.mat_mode[m]], s.hot_slot[N + m], cntV[m],
                                (T)(d.lambda_m * d.lambda_reg), s.meta_mslot[m], (T *)s.meta_rv[m]);
+    // sorted hot positions and chunk descriptors per tile
+    if (s.t_tiles > 0) {
+        auto ck = (N == 3) ? k_lf_chunks<uint2, 3> : k_lf_chunks<uint2, 4>;
+        hipLaunchKernelGGL(ck, dim3((unsigned)s.t_tiles), dim3(kTile), 0, st, s.meta_slot, nX, s.t_chunks,
+                           s.t_nchunks);
+    }
+    for (int m = 0; m < M; ++m)
+        if (s.m_tiles[m] > 0)
+            hipLaunchKernelGGL((k_lf_chunks<uint32_t, 2>), dim3((unsigned)s.m_tiles[m]), dim3(kTile), 0, st,
+                               s.meta_mslot[m], y_nnz[m], s.m_chunks[m], s.m_nchunks[m]);
+    if (hipGetLastError() != hipSuccess) {
+        err = "building the lock-free chunk tables failed";
+        return S3_ERR_HIP;
+    }
     s.ready = true;
     return S3_OK;
 }
@@ -724,6 +842,8 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
     L.tab_out = tab;
     L.core_out = core;
     L.meta_slot = s.meta_slot;
+    L.chunks = s.t_chunks;
+    L.nchunks = s.t_nchunks;
     L.meta_reg = (const T *)s.meta_reg;
     L.H = s.H;
     L.JP = s.JP;
@@ -758,15 +878,17 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
         Y.pb[m] = s.mpb[m];
         Y.tab_out[m] = (T *)s.tab_m[m];
         Y.meta_slot[m] = s.meta_mslot[m];
+        Y.chunks[m] = s.m_chunks[m];
+        Y.nchunks[m] = s.m_nchunks[m];
         Y.meta_rv[m] = (const T *)s.meta_rv[m];
         Y.gu[m] = s.mat_mode[m];
         Y.gv[m] = N + m;
         blocks += s.m_count[m];
     }
     if (blocks <= 0) return;
-    const size_t rep = (size_t)kRepSlots * kRep * (JP + 1);
-    const size_t smem = std::max((size_t)N * (s.H * (JP + 1) + rep) + (size_t)kTile * JP * N + 2,
-                                 (size_t)2 * (s.H * (JP + 1) + rep)) * sizeof(T);
+    const size_t W = (size_t)JP + 1;
+    const size_t smem = std::max((size_t)N * (s.H * W + kTile * W) + 2 * (kTile / kWave),
+                                 (size_t)2 * (s.H * W + kTile * W)) * sizeof(T);
     hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
                        count, eta, (T)(N + 1));
 }
