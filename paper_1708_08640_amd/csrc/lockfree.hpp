@@ -492,19 +492,26 @@ struct LFApplyArgs {
 };
 
 constexpr int kApplyThreads = 256;
+constexpr int kXcds = 8;  // workgroups are dealt to the XCDs round robin
 
 // blocks [0, groups * H): one hot row each; blocks after: 16 core elements
-// each (in the zero-padded JP^N layout)
+// each (in the zero-padded JP^N layout).  Neighbouring hot rows and core
+// chunks share cache lines of the partials, so the launch index is mapped
+// to give each XCD (and its L2) one contiguous range of them.
+S3_DEV int64_t lf_xcd_block(int64_t b, int64_t per_xcd) { return (b % kXcds) * per_xcd + b / kXcds; }
+
 template <int N, typename T>
 __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H, int JP, T *__restrict__ G,
                                                             T *__restrict__ Gp, int J0, int J1, int J2, int J3,
-                                                            T reg_core, T eta, T kappa) {
+                                                            T reg_core, T eta, T kappa, int64_t n_blocks) {
     constexpr int NW = kApplyThreads / kWave;
+    const int64_t blk = lf_xcd_block(blockIdx.x, gridDim.x / kXcds);
+    if (blk >= n_blocks) return;
     __shared__ T s_red[32 * NW];
     const int tid = threadIdx.x;
     const int nrowblk = a.groups * H;
-    if ((int)blockIdx.x < nrowblk) {
-        const int g = blockIdx.x / H, slot = blockIdx.x % H;
+    if (blk < nrowblk) {
+        const int g = (int)(blk / H), slot = (int)(blk % H);
         const int row = a.hot_row[g][slot];
         if (row < 0) return;  // uniform over the block
         // lane groups of KW lanes read one workgroup's JP + 1 contiguous
@@ -546,6 +553,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
         __syncthreads();
         if (tid >= a.J[g]) return;
         T gk = T(0), Lsum = T(0);
+#pragma unroll 4
         for (int w = 0; w < NW; ++w) {
             gk += s_red[w * 32 + tid];
             Lsum += s_red[w * 32 + JP];
@@ -559,26 +567,27 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
         return;
     }
     // core: lane el of phase ph sums element el of this block over the
-    // workgroups ph, ph + 16, ...; the phases are then added in order.  Every
+    // workgroups ph, ph + PH, ...; the phases are then added in order.  Every
     // lane also sums the two trailing entries (core curvature, entry count).
-    __shared__ T s_part[3][16][17];
+    constexpr int PH = kApplyThreads / 16;
+    __shared__ T s_part[3][PH][17];
     const int el = tid & 15, ph = tid >> 4;
     const int64_t cs = a.KP + 2;
-    const int64_t jp = (int64_t)(blockIdx.x - nrowblk) * 16 + el;
+    const int64_t jp = (blk - nrowblk) * 16 + el;
     const T *ct = (const T *)a.core_t;
     T e4[4] = {T(0), T(0), T(0), T(0)}, l4[4] = {T(0), T(0), T(0), T(0)}, c4[4] = {T(0), T(0), T(0), T(0)};
     const int64_t jr = jp < a.KP ? jp : a.KP;  // lanes past the end re-read a valid column
     int64_t b = ph;
-    for (; b + 48 < a.nwg_t; b += 64) {
+    for (; b + 3 * PH < a.nwg_t; b += 4 * PH) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const T *row = ct + (b + 16 * i) * cs;
+            const T *row = ct + (b + PH * i) * cs;
             e4[i] += row[jr];
             l4[i] += row[a.KP];
             c4[i] += row[a.KP + 1];
         }
     }
-    for (; b < a.nwg_t; b += 16) {
+    for (; b < a.nwg_t; b += PH) {
         const T *row = ct + b * cs;
         e4[0] += row[jr];
         l4[0] += row[a.KP];
@@ -590,7 +599,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
     __syncthreads();
     if (ph != 0 || jp >= a.KP) return;
     T gsum = T(0), LG = T(0), cnt = T(0);
-    for (int q = 0; q < 16; ++q) {
+#pragma unroll 4
+    for (int q = 0; q < PH; ++q) {
         gsum += s_part[0][q][el];
         LG += s_part[1][q][el];
         cnt += s_part[2][q][el];
@@ -939,9 +949,10 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
         }
         tensor_round(t0, t1 - t0, eta, st);  // tensor and matrix tiles, one launch
         const int64_t blocks = (int64_t)(N + M) * s.H + (s.KP + 15) / 16;
+        const int64_t grid = (blocks + kXcds - 1) / kXcds * kXcds;
         auto kern = (N == 3) ? k_lf_apply<3, T> : k_lf_apply<4, T>;
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kApplyThreads), 0, st, s.apply, s.H, s.JP,
-                           (T *)s.b.G, Gp, J[0], J[1], J[2], N > 3 ? J[3] : 1, reg_core, (T)eta, kappa);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kApplyThreads), 0, st, s.apply, s.H, s.JP,
+                           (T *)s.b.G, Gp, J[0], J[1], J[2], N > 3 ? J[3] : 1, reg_core, (T)eta, kappa, blocks);
     }
     return S3_OK;
 }
