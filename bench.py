@@ -37,6 +37,12 @@ def tensor_entry_flops(ranks):
     return 6 * K + 10 * sum(ranks)
 
 
+def matrix_entry_flops(rank):
+    """Prediction, error, both row gradients, curvatures and updates of one
+    coupled-matrix entry: about 10 flops per factor-row element."""
+    return 10 * rank
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -83,8 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed epochs before the timed ones")
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--mode", default="lockfree", choices=["lockfree", "det"])
-    ap.add_argument("--round-items", type=int, default=262144)
-    ap.add_argument("--hot-rows", type=int, default=128)
+    ap.add_argument("--round-items", type=int, default=524288)
+    ap.add_argument("--hot-rows", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -165,14 +171,18 @@ def main():
         if len(g["rmse"]) >= E:
             target = 1.01 * g["rmse"][E - 1]
 
-    flops = tensor_entry_flops(cfg.ranks) * p.n_train * args.steps
+    mat_flops = sum(matrix_entry_flops(cfg.ranks[s.mode]) * len(p.mat_val[m]) for m, s in enumerate(cfg.matrices))
+    # the lock-free tensor launch also runs the round's matrix tiles
+    flops = (tensor_entry_flops(cfg.ranks) * p.n_train + (mat_flops if args.mode == "lockfree" else 0)) * args.steps
     achieved = flops / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else None
     roofline = {
         "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_tensor",
         "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
         "traffic": profiled_traffic("k_lf_tensor") if args.mode == "lockfree" and cfg.name == "cfg2_zipf_10m" else None,
-        "flops_per_entry": tensor_entry_flops(cfg.ranks), "launches": launches,
+        "flops_per_tensor_entry": tensor_entry_flops(cfg.ranks),
+        "flops_per_matrix_entry": matrix_entry_flops(cfg.ranks[cfg.matrices[0].mode]) if cfg.matrices else None,
+        "launches": launches,
         "avg_launch_ms": kernel_ms / max(launches, 1), "kernel_share_of_epoch": kernel_ms / (t1 - t0) / 1e3,
     }
 
