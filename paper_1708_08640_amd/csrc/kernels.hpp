@@ -370,50 +370,174 @@ __global__ __launch_bounds__(512) void k_core_partial(TensorArgs<T> A, const int
     if (tid == 0) part_curv[blockIdx.x] = curv;
 }
 
-// G[j] -= eta * step, step = (sum_chunks P + nt * reg_core * G) / damp;
-// accumulate != 0: dG[j] += sum_chunks P (adjoint).
-template <int N, typename T>
-__global__ void k_core_apply(T *__restrict__ G, const T *__restrict__ part,
-                             const T *__restrict__ part_curv, int64_t nchunks, int JP, int J0,
-                             int J1, int J2, int J3, int64_t nt, T reg_core, T eta, T kappa,
-                             int damp, int accumulate) {
-    const int Js[4] = {J0, J1, J2, J3};
-    int K = 1, KP = 1;
-    for (int n = 0; n < N; ++n) { K *= Js[n]; KP *= JP; }
-    __shared__ T s_L;
-    if (threadIdx.x == 0) {
-        T L = T(0);
-        for (int64_t c = 0; c < nchunks; ++c) L += part_curv[c];
-        s_L = L + (T)nt * reg_core;
+// Core gradient of one 256-entry tile on the FP32 matrix cores:
+//   C[j1][tau] = sum_t (q u^(1))_t[j1] * (u^(2) o ... o u^(N))_t[tau]
+// as a (16 x 256) x (256 x 16 n-tiles) product with v_mfma_f32_16x16x4f32
+// (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 (l / 16) + r][l % 16]
+// in lane l, register r).  M = j1 (JP <= 16, zero padded), K = the tile's
+// entries, N = tail index tau; wave w takes n-tiles w, w + 4, ...; the
+// Khatri-Rao operand is formed from the LDS-staged rows as it is consumed.
+typedef float s3_v4f __attribute__((ext_vector_type(4)));
+
+template <int N, int JP>
+S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
+    constexpr int NW = kChunk / kWave;                    // waves per tile
+    constexpr int TPW = (NT + NW - 1) / NW;              // n-tiles per wave (max)
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int i16 = lane & 15, kq = lane >> 4;
+    s3_v4f acc[TPW];
+    int tj[TPW][N - 1];
+    bool tv[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        acc[q] = s3_v4f{0.f, 0.f, 0.f, 0.f};
+        const int tau = 16 * (wv + NW * q) + i16;
+        tv[q] = (wv + NW * q < NT) && tau < TAIL;
+        int r = tv[q] ? tau : 0;
+#pragma unroll
+        for (int n = N - 2; n >= 0; --n) { tj[q][n] = r % JP; r /= JP; }
     }
-    __syncthreads();
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < K; j += gridDim.x * blockDim.x) {
-        int rem = j, pj = 0, mul = 1;
-        for (int n = N - 1; n >= 0; --n) {
-            const int jn = rem % Js[n];
-            rem /= Js[n];
-            pj += jn * mul;
-            mul *= JP;
-        }
-        T s = T(0);
-        for (int64_t c = 0; c < nchunks; ++c) s += part[c * KP + pj];
-        if (accumulate) {
-            G[j] += s;
-        } else {
-            const T g = s + (T)nt * reg_core * G[j];
-            T scale = eta;
-            if (damp) {
-                const T d = kappa * eta * s_L;
-                scale = eta / (d > T(1) ? d : T(1));
+    for (int k0 = 0; k0 < kChunk; k0 += 4) {
+        const int t = k0 + kq;
+        const float a = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            if (wv + NW * q < NT) {  // uniform over the wave
+                float b = s_u[(t * (N - 1)) * JP + tj[q][0]];
+#pragma unroll
+                for (int n = 1; n < N - 1; ++n) b *= s_u[(t * (N - 1) + n) * JP + tj[q][n]];
+                b = tv[q] ? b : 0.f;
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
             }
-            G[j] -= scale * g;
         }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        if (!(wv + NW * q < NT)) continue;
+        const int tau = 16 * (wv + NW * q) + i16;
+        if (tau >= TAIL) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j1 = 4 * kq + r;
+            if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[q][r];
+        }
+    }
+}
+
+// FP32 det-mode core partial of one chunk on the matrix cores: the chunk's
+// operands are staged in LDS exactly as the lock-free tile does, and the
+// MFMA accumulation order is fixed, so runs stay bitwise reproducible.
+template <int N, int JP>
+__global__ __launch_bounds__(kChunk) void k_core_partial_mfma(TensorArgs<float> A, const int32_t *__restrict__ ids,
+                                                              int64_t nt, const float *__restrict__ scr,
+                                                              int64_t stride, float *__restrict__ part,
+                                                              float *__restrict__ part_curv) {
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    __shared__ float s_q[kChunk * JP];
+    __shared__ float s_u[kChunk * (N - 1) * JP];
+    __shared__ float s_c[kChunk / kWave];
+    const int tid = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * kChunk + tid;
+    float curv = 0.f;
+    if (s < nt) {
+        const int64_t e = ids[s];
+        const float q = scr[s * stride + stride - 2];
+        curv = scr[s * stride + stride - 1];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const float *r = A.U[n] + (int64_t)A.idx[(int64_t)n * A.nnz + e] * A.J[n];
+#pragma unroll
+            for (int k = 0; k < JP; ++k) {
+                const float v = (k < A.J[n]) ? r[k] : 0.f;
+                if (n == 0) s_q[tid * JP + k] = q * v;
+                else s_u[(tid * (N - 1) + n - 1) * JP + k] = v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = 0.f;
+#pragma unroll
+        for (int x = 0; x < (N - 1) * JP; ++x) s_u[tid * (N - 1) * JP + x] = 0.f;
+    }
+    curv = wave_sum(curv);
+    if ((tid & (kWave - 1)) == 0) s_c[tid / kWave] = curv;
+    __syncthreads();
+    core_tile_mfma<N, JP>(s_q, s_u, part + (int64_t)blockIdx.x * (JP * TAIL));
+    if (tid == 0) {
+        float c = 0.f;
+        for (int w = 0; w < kChunk / kWave; ++w) c += s_c[w];
+        part_curv[blockIdx.x] = c;
+    }
+}
+
+// G[j] -= eta * step, step = (sum_chunks P + nt * reg_core * G) / damp;
+// accumulate != 0: dG[j] += sum_chunks P (adjoint).  One block per 16 padded
+// core elements: lane el of phase ph sums chunks ph, ph + 16, ... of element
+// el (and of the curvature), then the phases are added in order.
+template <int N, typename T>
+__global__ __launch_bounds__(256) void k_core_apply(T *__restrict__ G, const T *__restrict__ part,
+                                                    const T *__restrict__ part_curv, int64_t nchunks, int JP,
+                                                    int J0, int J1, int J2, int J3, int64_t nt, T reg_core,
+                                                    T eta, T kappa, int damp, int accumulate) {
+    __shared__ T s_p[2][16][17];
+    const int Js[4] = {J0, J1, J2, J3};
+    int64_t KP = 1;
+    for (int n = 0; n < N; ++n) KP *= JP;
+    const int el = threadIdx.x & 15, ph = threadIdx.x >> 4;
+    const int64_t pj = (int64_t)blockIdx.x * 16 + el;
+    const int64_t pr = pj < KP ? pj : 0;
+    T s0 = T(0), s1 = T(0), L0 = T(0), L1 = T(0);
+    int64_t c = ph;
+    for (; c + 16 < nchunks; c += 32) {
+        s0 += part[c * KP + pr];
+        s1 += part[(c + 16) * KP + pr];
+        L0 += part_curv[c];
+        L1 += part_curv[c + 16];
+    }
+    for (; c < nchunks; c += 16) {
+        s0 += part[c * KP + pr];
+        L0 += part_curv[c];
+    }
+    s_p[0][ph][el] = s0 + s1;
+    s_p[1][ph][el] = L0 + L1;
+    __syncthreads();
+    if (ph != 0 || pj >= KP) return;
+    T s = T(0), L = T(0);
+    for (int q = 0; q < 16; ++q) {
+        s += s_p[0][q][el];
+        L += s_p[1][q][el];
+    }
+    // padded index -> core index (the padding has no element)
+    int64_t rem = pj, j = 0, mul = 1;
+    for (int n = N - 1; n >= 0; --n) {
+        const int jn = (int)(rem % JP);
+        rem /= JP;
+        if (jn >= Js[n]) return;
+        j += jn * mul;
+        mul *= Js[n];
+    }
+    if (accumulate) {
+        G[j] += s;
+    } else {
+        const T g = s + (T)nt * reg_core * G[j];
+        T scale = eta;
+        if (damp) {
+            const T d = kappa * eta * (L + (T)nt * reg_core);
+            scale = eta / (d > T(1) ? d : T(1));
+        }
+        G[j] -= scale * g;
     }
 }
 
 // ---------------------------------------------------------- det: rows apply
 
-// One wavefront per touched row (segment) of the batch.
+// One wavefront per touched row (segment) of the batch; segments of more
+// than kLongSeg contributions (the power-law head rows) are left to
+// k_rows_apply_long.
+constexpr int64_t kLongSeg = 512;
+
 template <typename T, int JMAX>
 __global__ __launch_bounds__(256) void k_rows_apply(const uint64_t *__restrict__ contrib,
                                                     const int64_t *__restrict__ seg_start,
@@ -426,6 +550,7 @@ __global__ __launch_bounds__(256) void k_rows_apply(const uint64_t *__restrict__
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
     for (int64_t s = s0 + wid; s < s1; s += nw) {
         const int64_t c0 = seg_start[s], c1 = seg_start[s + 1];
+        if (c1 - c0 > kLongSeg) continue;  // uniform over the wavefront
         T acc[JMAX];
 #pragma unroll
         for (int k = 0; k < JMAX; ++k) acc[k] = T(0);
@@ -459,6 +584,86 @@ __global__ __launch_bounds__(256) void k_rows_apply(const uint64_t *__restrict__
             }
         }
     }
+}
+
+// One 1,024-thread block per long segment (listed at bind time): thread t
+// sums contributions t, t + 1024, ... two at a time; the wavefronts are then
+// added in order, so the result is reproducible.
+constexpr int kLongThreads = 1024;
+
+template <typename T, int JMAX>
+__global__ __launch_bounds__(kLongThreads) void k_rows_apply_long(
+    const uint64_t *__restrict__ contrib, const int64_t *__restrict__ seg_start, const int32_t *__restrict__ seg_row,
+    const int32_t *__restrict__ long_ids, int64_t l0, const T *__restrict__ scr, T *__restrict__ P, int J, T eta,
+    T kappa, int damp, int accumulate) {
+    constexpr int NW = kLongThreads / kWave;
+    __shared__ T s_red[NW][JMAX + 1];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t s = long_ids[l0 + blockIdx.x];
+    const int64_t c0 = seg_start[s], c1 = seg_start[s + 1];
+    T acc[JMAX + 1];
+#pragma unroll
+    for (int k = 0; k <= JMAX; ++k) acc[k] = T(0);
+    int64_t c = c0 + tid;
+    for (; c + kLongThreads < c1; c += 2 * kLongThreads) {
+        const uint64_t v0 = contrib[c], v1 = contrib[c + kLongThreads];
+        const T *g0 = scr + (int64_t)(v0 & 0xffffffffull);
+        const T *g1 = scr + (int64_t)(v1 & 0xffffffffull);
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k)
+            if (k < J) acc[k] += g0[k] + g1[k];
+        acc[JMAX] += scr[(int64_t)(v0 >> 32)] + scr[(int64_t)(v1 >> 32)];
+    }
+    if (c < c1) {
+        const uint64_t v = contrib[c];
+        const T *g = scr + (int64_t)(v & 0xffffffffull);
+#pragma unroll
+        for (int k = 0; k < JMAX; ++k)
+            if (k < J) acc[k] += g[k];
+        acc[JMAX] += scr[(int64_t)(v >> 32)];
+    }
+#pragma unroll
+    for (int k = 0; k <= JMAX; ++k) {
+        const T t = wave_sum(acc[k]);
+        if (lane == 0) s_red[wv][k] = t;
+    }
+    __syncthreads();
+    if (tid >= J) return;
+    T mine = T(0), L = T(0);
+    for (int w = 0; w < NW; ++w) {
+        mine += s_red[w][tid];
+        L += s_red[w][JMAX];
+    }
+    T *p = P + (int64_t)seg_row[s] * J + tid;
+    if (accumulate) {
+        *p += mine;
+    } else {
+        T scale = eta;
+        if (damp) {
+            const T d = kappa * eta * L;
+            scale = eta / (d > T(1) ? d : T(1));
+        }
+        *p -= scale * mine;
+    }
+}
+
+// bind time: the segments longer than kLongSeg, in order, with their batch
+__global__ void k_long_flags(const int64_t *__restrict__ seg_start, int64_t nseg, int32_t *__restrict__ flag) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; s < nseg; s += stride) flag[s] = (seg_start[s + 1] - seg_start[s] > kLongSeg) ? 1 : 0;
+}
+
+__global__ void k_long_write(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t nseg,
+                             const uint32_t *__restrict__ seg_batch, int32_t *__restrict__ long_ids,
+                             uint32_t *__restrict__ long_batch) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; s < nseg; s += stride)
+        if (flag[s]) {
+            long_ids[pos[s] - 1] = (int32_t)s;
+            long_batch[pos[s] - 1] = seg_batch[s];
+        }
 }
 
 // ---------------------------------------------------------------- evaluation

@@ -261,62 +261,6 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
     for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
 }
 
-// Core gradient of one 256-entry tile on the FP32 matrix cores:
-//   C[j1][tau] = sum_t (q u^(1))_t[j1] * (u^(2) o ... o u^(N))_t[tau]
-// as a (16 x 256) x (256 x 16 n-tiles) product with v_mfma_f32_16x16x4f32
-// (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 (l / 16) + r][l % 16]
-// in lane l, register r).  M = j1 (JP <= 16, zero padded), K = the tile's
-// entries, N = tail index tau; wave w takes n-tiles w, w + 4, ...; the
-// Khatri-Rao operand is formed from the LDS-staged rows as it is consumed.
-typedef float s3_v4f __attribute__((ext_vector_type(4)));
-
-template <int N, int JP>
-S3_DEV void lf_core_tile_mfma(const float *s_q, const float *s_u, float *core) {
-    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
-    constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
-    constexpr int NW = kTile / kWave;                    // waves per tile
-    constexpr int TPW = (NT + NW - 1) / NW;              // n-tiles per wave (max)
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int i16 = lane & 15, kq = lane >> 4;
-    s3_v4f acc[TPW];
-    int tj[TPW][N - 1];
-    bool tv[TPW];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        acc[q] = s3_v4f{0.f, 0.f, 0.f, 0.f};
-        const int tau = 16 * (wv + NW * q) + i16;
-        tv[q] = (wv + NW * q < NT) && tau < TAIL;
-        int r = tv[q] ? tau : 0;
-#pragma unroll
-        for (int n = N - 2; n >= 0; --n) { tj[q][n] = r % JP; r /= JP; }
-    }
-    for (int k0 = 0; k0 < kTile; k0 += 4) {
-        const int t = k0 + kq;
-        const float a = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            if (wv + NW * q < NT) {  // uniform over the wave
-                float b = s_u[(t * (N - 1)) * JP + tj[q][0]];
-#pragma unroll
-                for (int n = 1; n < N - 1; ++n) b *= s_u[(t * (N - 1) + n) * JP + tj[q][n]];
-                b = tv[q] ? b : 0.f;
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        if (!(wv + NW * q < NT)) continue;
-        const int tau = 16 * (wv + NW * q) + i16;
-        if (tau >= TAIL) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j1 = 4 * kq + r;
-            if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[q][r];
-        }
-    }
-}
-
 // ------------------------------------------------------------------ tensor
 
 // Blocks [0, n_tensor): tensor tiles.  Blocks after: the round's matrix
@@ -430,7 +374,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
     __syncthreads();
     T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
     if constexpr (std::is_same<T, float>::value) {
-        lf_core_tile_mfma<N, JP>(s_q, s_u, core);
+        core_tile_mfma<N, JP>(s_q, s_u, core);
     } else {
         // core gradient of this tile on the VALU: work item = (tail index tau
         // over modes 2..N, slice of JS consecutive mode-1 indices)

@@ -27,9 +27,11 @@ struct Group {
     uint64_t *contrib = nullptr;  // sorted (goff | coff << 32)
     int64_t *seg_start = nullptr; // [nseg + 1]
     int32_t *seg_row = nullptr;   // [nseg]
+    int32_t *long_ids = nullptr;  // segments longer than kLongSeg, in order
     int64_t n_valid = 0;
     int64_t nseg = 0;
     std::vector<int64_t> h_boff;  // per-batch segment ranges
+    std::vector<int64_t> h_loff;  // per-batch ranges of long_ids
     int J = 0;
     int64_t rows = 0;
 };
@@ -162,8 +164,12 @@ template <int N, int JP, typename T> struct Impl {
         constexpr int TPB = ((TAIL + 63) / 64) * 64;
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
         const int64_t nch = (nt + kChunk - 1) / kChunk;
-        hipLaunchKernelGGL((k_core_partial<N, JP, T>), dim3((unsigned)nch), dim3(TPB), 0, st, a, ids, nt,
-                           (const T *)p->scr, p->t_stride, (T *)p->part, (T *)p->part_curv);
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL((k_core_partial_mfma<N, JP>), dim3((unsigned)nch), dim3(kChunk), 0, st, a, ids, nt,
+                               (const float *)p->scr, p->t_stride, (float *)p->part, (float *)p->part_curv);
+        else
+            hipLaunchKernelGGL((k_core_partial<N, JP, T>), dim3((unsigned)nch), dim3(TPB), 0, st, a, ids, nt,
+                               (const T *)p->scr, p->t_stride, (T *)p->part, (T *)p->part_curv);
     }
     static void sq_err(s3_plan *p, const int32_t *idx, const void *val, int64_t nnz, double *part,
                        hipStream_t st) {
@@ -237,14 +243,20 @@ double eta_of(const s3_desc &d, int epoch) { return d.eta0 / (1.0 + d.mu * (doub
 
 // launch helper for the row-apply kernel (J <= 16)
 template <typename T>
-void rows_apply(const Group &g, int64_t s0, int64_t s1, const void *scr, void *P, double eta, double kappa,
-                int damp, int acc, hipStream_t st) {
+void rows_apply(const Group &g, int64_t b, const void *scr, void *P, double eta, double kappa, int damp, int acc,
+                hipStream_t st) {
+    const int64_t s0 = g.h_boff[b], s1 = g.h_boff[b + 1];
     const int64_t nseg = s1 - s0;
     if (nseg <= 0) return;
     const int tpb = 256;
     hipLaunchKernelGGL((k_rows_apply<T, 16>), dim3(grid_for(nseg * kWave, tpb, 1ll << 20)), dim3(tpb), 0, st,
                        g.contrib, g.seg_start, g.seg_row, s0, s1, (const T *)scr, (T *)P, g.J, (T)eta,
                        (T)kappa, damp, acc);
+    const int64_t l0 = g.h_loff[b], nl = g.h_loff[b + 1] - l0;
+    if (nl > 0)
+        hipLaunchKernelGGL((k_rows_apply_long<T, 16>), dim3((unsigned)nl), dim3(kLongThreads), 0, st, g.contrib,
+                           g.seg_start, g.seg_row, g.long_ids, l0, (const T *)scr, (T *)P, g.J, (T)eta, (T)kappa,
+                           damp, acc);
 }
 
 template <typename T>
@@ -253,7 +265,7 @@ void core_apply(s3_plan *p, int64_t nt, double eta, int acc, void *dst, hipStrea
     const double reg_core = p->d.lambda_reg / (double)p->nX;
     const int *J = p->d.rank;
     auto kern = (p->N == 3) ? k_core_apply<3, T> : k_core_apply<4, T>;
-    hipLaunchKernelGGL(kern, dim3(grid_for(p->K, 256, 64)), dim3(256), 0, st, (T *)dst, (const T *)p->part,
+    hipLaunchKernelGGL(kern, dim3((unsigned)((p->KP + 15) / 16)), dim3(256), 0, st, (T *)dst, (const T *)p->part,
                        (const T *)p->part_curv, nch, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1, nt,
                        (T)reg_core, (T)eta, (T)(p->N + 1), p->d.damping, acc);
 }
@@ -307,8 +319,7 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
     for (int g = 0; g < p->N + M; ++g) {
         const Group &G = p->grp[g];
         void *P = (g < p->N) ? (adj ? dU[g] : p->b.U[g]) : (adj ? dV[g - p->N] : p->b.V[g - p->N]);
-        rows_apply<T>(G, G.h_boff[b], G.h_boff[b + 1], p->scr, P, eta, (double)(p->N + 1), p->d.damping,
-                      adj ? 1 : 0, st);
+        rows_apply<T>(G, b, p->scr, P, eta, (double)(p->N + 1), p->d.damping, adj ? 1 : 0, st);
     }
     if (nt > 0) core_apply<T>(p, nt, eta, adj ? 1 : 0, adj ? dG : p->b.G, st);
 }
@@ -477,6 +488,7 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
             p->grp[g].contrib = c.take<uint64_t>((size_t)std::max<int64_t>(nv, 1));
             p->grp[g].seg_start = c.take<int64_t>((size_t)nv + 1);
             p->grp[g].seg_row = c.take<int32_t>((size_t)std::max<int64_t>(nv, 1));
+            p->grp[g].long_ids = c.take<int32_t>((size_t)(nv / kLongSeg + 1));
         }
         // per-batch scratch
         const int64_t RJ = (int64_t)N * p->JP;  // gradient rows at a fixed JP stride
@@ -576,6 +588,7 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
         HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(temp, tb, gk_in, gk_out, gv_in, gv_out, (int)n, 0, 64, st));
         const int64_t nv = G.n_valid;
         G.h_boff.assign((size_t)nb + 1, 0);
+        G.h_loff.assign((size_t)nb + 1, 0);
         if (nv == 0) { G.nseg = 0; continue; }
         HIPCHK(p, hipMemcpyAsync(G.contrib, gv_out, sizeof(uint64_t) * nv, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, st, gk_out, nv, flags);
@@ -589,6 +602,22 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
         hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(G.nseg + 1, 256, 16384)), dim3(256), 0, st, segb,
                            G.nseg, nb, boff);
         HIPCHK(p, hipMemcpyAsync(G.h_boff.data(), boff, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        // the long segments (one block each at apply time), per batch
+        if (G.nseg == 0) continue;
+        hipLaunchKernelGGL(k_long_flags, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, G.seg_start, G.nseg,
+                           flags);
+        HIPCHK(p, hipcub::DeviceScan::InclusiveSum(temp, tb, flags, segid, (int)G.nseg, st));
+        int32_t nlong = 0;
+        HIPCHK(p, hipMemcpyAsync(&nlong, segid + G.nseg - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        if (nlong == 0) continue;
+        uint32_t *lbatch = (uint32_t *)gk_in;  // free once this group's keys are sorted
+        hipLaunchKernelGGL(k_long_write, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, flags, segid,
+                           G.nseg, segb, G.long_ids, lbatch);
+        hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(nlong + 1, 256, 16384)), dim3(256), 0, st, lbatch,
+                           (int64_t)nlong, nb, boff);
+        HIPCHK(p, hipMemcpyAsync(G.h_loff.data(), boff, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st));
         HIPCHK(p, hipStreamSynchronize(st));
     }
     p->det_ready = true;
