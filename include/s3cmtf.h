@@ -213,6 +213,16 @@ s3_status s3_backward(s3_plan *plan, const void *gx, const void *const *gy,
 s3_status s3_export(s3_plan *plan, int32_t which, int32_t index, double *host_dst,
                     size_t bytes, void *stream);
 
+/* Orthogonalise the bound parameters in place (Algorithm 1, closing step):
+ * every factor U^(n) = Q R becomes Q (orthonormal columns), the core becomes
+ * G x_n R for every mode n, and every coupled V_m becomes V_m R^(c_m)T, so
+ * all predictions are unchanged.  QR is CholeskyQR2 with the Gram matrix,
+ * Cholesky factor and R^-1 in FP64 (R has a positive diagonal, so Q is
+ * unique).  Needs J_n <= min(16, I_n) (else S3_ERR_UNSUPPORTED); a factor
+ * that is not numerically full rank gives S3_ERR_NONFINITE and is left
+ * partly transformed.  Synchronous.                                        */
+s3_status s3_orthogonalize(s3_plan *plan, void *stream);
+
 /* BF16 plans: round the float masters to the bf16 working copies
  * (round-to-nearest-even).  Call after filling the masters.  Asynchronous. */
 s3_status s3_sync_bf16(s3_plan *plan, void *stream);

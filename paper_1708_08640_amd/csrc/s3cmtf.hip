@@ -16,6 +16,7 @@
 
 #include "kernels.hpp"
 #include "lockfree.hpp"
+#include "qr.hpp"
 
 using namespace s3;
 
@@ -94,6 +95,9 @@ struct s3_plan {
     bool det_ready = false;
     // lock-free structures
     LockFreeState lf;
+    // orthogonalisation: Gram partials, per mode R / R^-1 / running R, a core copy
+    double *qr_part = nullptr, *qr_R = nullptr;
+    void *qr_G = nullptr;
     // profiling
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
@@ -472,6 +476,10 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
     const int64_t nb = (n_items + B - 1) / B;
     // lock-free structures
     lockfree_layout<T>(p->lf, c, N, M, p->d, x_nnz, y_nnz, p->KP, p->JP);
+    // orthogonalisation
+    p->qr_part = c.take<double>((size_t)kQrBlocks * kQrJ * kQrJ);
+    p->qr_R = c.take<double>((size_t)N * 3 * kQrJ * kQrJ);
+    p->qr_G = c.take<T>((size_t)p->K);
     if (with_order) {
         p->sorted_ids = c.take<int32_t>((size_t)n_items);
         // groups
@@ -969,6 +977,56 @@ s3_status s3_export(s3_plan *p, int32_t which, int32_t index, double *host_dst, 
         for (int64_t i = 0; i < count; ++i) host_dst[i] = (double)tmp[(size_t)i];
     }
     return S3_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T> s3_status orthogonalize_impl(s3_plan *p, hipStream_t st) {
+    const int N = p->N;
+    const int *J = p->d.rank;
+    HIPCHK(p, hipMemsetAsync(p->flag, 0, sizeof(int32_t), st));
+    for (int n = 0; n < N; ++n) {
+        double *R = p->qr_R + (size_t)n * 3 * kQrJ * kQrJ, *Rinv = R + kQrJ * kQrJ, *Rtot = Rinv + kQrJ * kQrJ;
+        const int64_t I = p->d.dims[n];
+        const int nb = (int)std::min<int64_t>(kQrBlocks, std::max<int64_t>(1, (I + kQrRows - 1) / kQrRows));
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_gram<T>, dim3(nb), dim3(256), 0, st, (const T *)p->b.U[n], I, J[n], p->qr_part);
+            hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, st, (const double *)p->qr_part, nb, J[n], R, Rinv,
+                               Rtot, pass == 0 ? 1 : 0, p->flag);
+            hipLaunchKernelGGL(k_apply_rinv<T>, dim3(grid_for(I, 256, 4096)), dim3(256), 0, st, (T *)p->b.U[n], I,
+                               J[n], (const double *)Rinv);
+        }
+        // G <- G x_n R
+        HIPCHK(p, hipMemcpyAsync(p->qr_G, p->b.G, sizeof(T) * p->K, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_core_mode_mul<T>, dim3(grid_for(p->K, 256, 64)), dim3(256), 0, st, (const T *)p->qr_G,
+                           (T *)p->b.G, N, J[0], J[1], J[2], N > 3 ? J[3] : 1, n, (const double *)Rtot);
+    }
+    for (int m = 0; m < p->M; ++m) {
+        const int c = p->d.mat_mode[m];
+        const double *Rtot = p->qr_R + (size_t)c * 3 * kQrJ * kQrJ + 2 * kQrJ * kQrJ;
+        hipLaunchKernelGGL(k_rows_times_rt<T>, dim3(grid_for(p->d.mat_cols[m], 256, 4096)), dim3(256), 0, st,
+                           (T *)p->b.V[m], (int64_t)p->d.mat_cols[m], J[c], Rtot);
+    }
+    HIPCHK(p, hipGetLastError());
+    int32_t bad = 0;
+    HIPCHK(p, hipMemcpyAsync(&bad, p->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipStreamSynchronize(st));
+    if (bad) return fail(p, S3_ERR_NONFINITE, "orthogonalisation: a factor matrix is not numerically full rank");
+    return S3_OK;
+}
+}  // namespace
+
+extern "C" {
+
+s3_status s3_orthogonalize(s3_plan *p, void *stream) {
+    if (!p) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_orthogonalize before s3_bind");
+    for (int n = 0; n < p->N; ++n)
+        if (p->d.rank[n] > kQrJ || p->d.rank[n] > p->d.dims[n])
+            return fail(p, S3_ERR_UNSUPPORTED, "orthogonalisation needs J_n <= min(16, I_n)");
+    hipStream_t st = (hipStream_t)stream;
+    return p->tsize == 8 ? orthogonalize_impl<double>(p, st) : orthogonalize_impl<float>(p, st);
 }
 
 s3_status s3_sync_bf16(s3_plan *p, void *stream) {

@@ -206,6 +206,11 @@ class S3Plan:
                                  out.nbytes, _stream()), self.h)
         return out
 
+    def orthogonalize(self) -> None:
+        """Algorithm 1's closing step on the device: U <- Q, G <- G x_n R,
+        V <- V R^T (predictions unchanged)."""
+        check(self.lib.s3_orthogonalize(self.h, _stream()), self.h)
+
     def params_numpy(self):
         return ([self.export("U", n) for n in range(len(self.U))], self.export("G"),
                 [self.export("V", m) for m in range(len(self.V))])
