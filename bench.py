@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--round-items", type=int, default=524288)
     ap.add_argument("--hot-rows", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--contraction", default="reuse", choices=["reuse", "naive"],
+                    help="naive: the per-entry contraction without reuse of partial products (ablation)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
@@ -131,7 +133,8 @@ def main():
     log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {n_updates - p.n_train:,} matrix entries")
     order = item_order(p.n_items, args.seed, 0) if args.mode == "det" else None
     plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", batch=args.batch, order=order, damping=True,
-                               round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows)
+                               round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows,
+                               contraction=args.contraction)
     torch.cuda.synchronize()
     rmse0 = plan.rmse()
     log(f"bound; initial held-out RMSE {rmse0:.4f}")
@@ -200,6 +203,7 @@ def main():
                    "round_items": args.round_items if args.mode == "lockfree" else None,
                    "hot_rows": args.hot_rows if args.mode == "lockfree" else None,
                    "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
+                   "contraction": args.contraction,
                    "updates_per_epoch": n_updates, "parallelism": "single GPU"},
         "heldout_rmse": rmse, "heldout_rmse_init": rmse0, "rmse_epochs": E, "rmse_target": target,
         "rmse_ok": (rmse <= target) if target is not None else None,

@@ -96,6 +96,10 @@ enum { S3_DAMP_NONE = 0, S3_DAMP_CURVATURE = 1 };       /* s3_desc.damping */
  * core of one entry).  The lock-free mode always damps.  (Not in the paper:
  * a reading needed to keep thousands of concurrent updates of power-law-hot
  * rows stable.)                                                            */
+/* Per-entry contraction (s3_desc.contraction). */
+#define S3_CONTRACT_REUSE 0
+#define S3_CONTRACT_NAIVE 1
+
 typedef struct {
     int32_t order;                       /* N: 3 or 4                        */
     int32_t n_mat;                       /* M: 0..S3_MAX_MATRICES            */
@@ -113,6 +117,13 @@ typedef struct {
                                             per-round hot tables (0: as many as
                                             the LDS budget allows, <= 256; -1:
                                             none, every row is updated at once) */
+    int32_t contraction;                 /* S3_CONTRACT_REUSE (default) or
+                                            S3_CONTRACT_NAIVE: the per-entry
+                                            contraction without reuse of partial
+                                            products (Algorithm 2's cost, an
+                                            ablation of Lemma 4; N = 3 with
+                                            J <= 4 or J = 10, N = 4 with J <= 2,
+                                            else S3_ERR_UNSUPPORTED)          */
 } s3_desc;
 
 /* Device buffers handed to s3_bind.  Values and parameters are `double` for

@@ -94,6 +94,51 @@ S3_DEV void contract(GP G, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {
     }
 }
 
+// Ablation baseline without reuse: x~ and every w_n each take their own
+// pass over the core, forming every term from the factor entries afresh
+// (the per-entry work of the paper's naive form, Algorithm 2, whose cost
+// Lemma 4 compares with the reuse of Algorithm 3).  (N + 1) passes of Jᴺ
+// terms with N - 1 products each, against 2 Jᴺ FMAs above.
+template <int N, int JP, typename T, typename GP>
+S3_DEV void contract_naive(GP G, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {
+    T x = T(0);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; ++k) w[n][k] = T(0);
+    if constexpr (N == 3) {
+#pragma unroll
+        for (int j1 = 0; j1 < JP; ++j1)
+#pragma unroll
+            for (int j2 = 0; j2 < JP; ++j2)
+#pragma unroll
+                for (int j3 = 0; j3 < JP; ++j3) {
+                    const T g = G[(j1 * JP + j2) * JP + j3];
+                    x = fmaT(g, u[0][j1] * u[1][j2] * u[2][j3], x);
+                    w[0][j1] = fmaT(g, u[1][j2] * u[2][j3], w[0][j1]);
+                    w[1][j2] = fmaT(g, u[0][j1] * u[2][j3], w[1][j2]);
+                    w[2][j3] = fmaT(g, u[0][j1] * u[1][j2], w[2][j3]);
+                }
+    } else {
+#pragma unroll
+        for (int j1 = 0; j1 < JP; ++j1)
+#pragma unroll
+            for (int j2 = 0; j2 < JP; ++j2)
+#pragma unroll
+                for (int j3 = 0; j3 < JP; ++j3)
+#pragma unroll
+                    for (int j4 = 0; j4 < JP; ++j4) {
+                        const T g = G[((j1 * JP + j2) * JP + j3) * JP + j4];
+                        x = fmaT(g, u[0][j1] * u[1][j2] * u[2][j3] * u[3][j4], x);
+                        w[0][j1] = fmaT(g, u[1][j2] * u[2][j3] * u[3][j4], w[0][j1]);
+                        w[1][j2] = fmaT(g, u[0][j1] * u[2][j3] * u[3][j4], w[1][j2]);
+                        w[2][j3] = fmaT(g, u[0][j1] * u[1][j2] * u[3][j4], w[2][j3]);
+                        w[3][j4] = fmaT(g, u[0][j1] * u[1][j2] * u[2][j3], w[3][j4]);
+                    }
+    }
+    xhat = x;
+}
+
 // prediction only (Eq 4): same pass without the w_n outputs for outer modes
 template <int N, int JP, typename T, typename GP>
 S3_DEV T predict(GP G, const T (&u)[N][JP]) {

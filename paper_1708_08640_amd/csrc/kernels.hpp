@@ -229,7 +229,7 @@ S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t 
 // regulariser).  The mode is a template flag and the entry's value is loaded
 // before the contraction: with a run-time choice between two loads after it
 // the compiler front-loads every scalar core load and spills them.
-template <int N, int JP, typename T, bool ADJ>
+template <int N, int JP, typename T, bool ADJ, bool NAIVE = false>
 __global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32_t *__restrict__ ids,
                                                     int64_t nt, const T *__restrict__ Gp,
                                                     T *__restrict__ scr, int64_t stride,
@@ -242,7 +242,8 @@ __global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32
         load_rows<N, JP, T>(A, e, u, rows);
         const T xv = ADJ ? gx[e] : A.val[e];
         T xhat;
-        contract<N, JP, T>(Gp, u, w, xhat);
+        if constexpr (NAIVE) contract_naive<N, JP, T>(Gp, u, w, xhat);
+        else contract<N, JP, T>(Gp, u, w, xhat);
         constexpr bool train = !ADJ;
         const T q = train ? -(xv - xhat) : xv;
         // fixed JP stride per mode (padding lanes hold zeros): stores at

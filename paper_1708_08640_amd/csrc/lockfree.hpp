@@ -270,7 +270,7 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
 // three 256-thread workgroups per CU the LDS allows), 1 otherwise
 template <int N, int JP> constexpr int lf_min_waves() { return ((N == 3 ? JP * JP * JP : JP * JP * JP * JP) <= 1024) ? 3 : 1; }
 
-template <int N, int JP, typename T, bool EXACT>
+template <int N, int JP, typename T, bool EXACT, bool NAIVE = false>
 __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
                                                                           LFArgs<T> L, LFMatArgs<T> Y,
                                                                           int64_t n_tensor, T eta, T kappa) {
@@ -314,7 +314,8 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
 #pragma unroll
         for (int n = 0; n < N; ++n) regs[n] = L.meta_reg[(int64_t)n * A.nnz + e];
         T xhat;
-        contract<N, JP, T>(Gp, u, w, xhat);
+        if constexpr (NAIVE) contract_naive<N, JP, T>(Gp, u, w, xhat);
+        else contract<N, JP, T>(Gp, u, w, xhat);
         q = -(xv - xhat);
         LG = T(1);
 #pragma unroll
@@ -808,7 +809,7 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
     return L;
 }
 
-template <int N, int JP, typename T, bool EXACT>
+template <int N, int JP, typename T, bool EXACT, bool NAIVE = false>
 void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
                             T eta, hipStream_t st) {
     LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
@@ -843,7 +844,7 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
     const size_t W = (size_t)JP + 1;
     const size_t smem = std::max((size_t)N * (s.H * W + kTile * W) + 2 * (kTile / kWave),
                                  (size_t)2 * (s.H * W + kTile * W)) * sizeof(T);
-    hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
+    hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT, NAIVE>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
                        count, eta, (T)(N + 1));
 }
 

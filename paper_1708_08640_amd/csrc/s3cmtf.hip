@@ -153,15 +153,18 @@ template <typename T> TensorArgs<T> tensor_args(const s3_plan *p, const int32_t 
     return a;
 }
 
-template <int N, int JP, typename T> struct Impl {
+// NAIVE: the contraction without reuse (ablation); it changes only the
+// per-entry training kernels
+template <int N, int JP, typename T, bool NAIVE = false> struct Impl {
     static void det_tensor(s3_plan *p, const int32_t *ids, int64_t nt, const void *gx, hipStream_t st) {
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
         if (gx)
-            hipLaunchKernelGGL((k_det_tensor<N, JP, T, true>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256), 0,
-                               st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
+            hipLaunchKernelGGL((k_det_tensor<N, JP, T, true, NAIVE>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256),
+                               0, st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
         else
-            hipLaunchKernelGGL((k_det_tensor<N, JP, T, false>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256), 0,
-                               st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)nullptr);
+            hipLaunchKernelGGL((k_det_tensor<N, JP, T, false, NAIVE>), dim3(grid_for(nt, 256, 1ll << 30)),
+                               dim3(256), 0, st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride,
+                               (const T *)nullptr);
     }
     static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
         constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
@@ -188,20 +191,31 @@ template <int N, int JP, typename T> struct Impl {
     }
     static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st) {
         if (p->exact)
-            lockfree_tensor_launch<N, JP, T, true>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                                   (const T *)p->Gp, first, count, (T)eta, st);
+            lockfree_tensor_launch<N, JP, T, true, NAIVE>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+                                                          (const T *)p->Gp, first, count, (T)eta, st);
         else
-            lockfree_tensor_launch<N, JP, T, false>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                                    (const T *)p->Gp, first, count, (T)eta, st);
+            lockfree_tensor_launch<N, JP, T, false, NAIVE>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+                                                           (const T *)p->Gp, first, count, (T)eta, st);
     }
 };
 
-template <int N, int JP, typename T> KernelSet make_set() {
-    return KernelSet{&Impl<N, JP, T>::det_tensor, &Impl<N, JP, T>::core_partial, &Impl<N, JP, T>::sq_err,
-                     &Impl<N, JP, T>::predict, &Impl<N, JP, T>::lf_tensor};
+template <int N, int JP, typename T, bool NAIVE = false> KernelSet make_set() {
+    using I = Impl<N, JP, T, NAIVE>;
+    return KernelSet{&I::det_tensor, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor};
 }
 
-template <typename T> bool pick_set(int N, int JP, KernelSet *ks) {
+// the ablation's kernels exist for the shapes of the tests and of the
+// 10M-entry workload only
+template <typename T> bool pick_naive_set(int N, int JP, KernelSet *ks) {
+    if (N == 3 && JP == 3) { *ks = make_set<3, 3, T, true>(); return true; }
+    if (N == 3 && JP == 4) { *ks = make_set<3, 4, T, true>(); return true; }
+    if (N == 3 && JP == 10) { *ks = make_set<3, 10, T, true>(); return true; }
+    if (N == 4 && JP == 2) { *ks = make_set<4, 2, T, true>(); return true; }
+    return false;
+}
+
+template <typename T> bool pick_set(int N, int JP, KernelSet *ks, bool naive) {
+    if (naive) return pick_naive_set<T>(N, JP, ks);
     if (N == 3) {
         switch (JP) {
         case 3: *ks = make_set<3, 3, T>(); return true;
@@ -366,6 +380,7 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     if (d.dtype != S3_F64 && d.dtype != S3_F32 && d.dtype != S3_BF16) return S3_ERR_UNSUPPORTED;
     if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
     if (d.batch < 1 || d.round_items < 1 || d.hot_rows < -1 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
+    if (d.contraction != S3_CONTRACT_REUSE && d.contraction != S3_CONTRACT_NAIVE) return S3_ERR_INVALID_ARG;
     if (!(d.eta0 > 0) || !(d.mu >= 0) || !(d.lambda_reg >= 0) || !(d.lambda_m >= 0)) return S3_ERR_INVALID_ARG;
     int Jmax = 0;
     for (int n = 0; n < d.order; ++n) {
@@ -387,7 +402,9 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     p->exact = true;
     for (int n = 0; n < p->N; ++n) p->exact = p->exact && d.rank[n] == JP;
     p->tsize = (d.dtype == S3_F64) ? 8 : 4;
-    const bool ok = (d.dtype == S3_F64) ? pick_set<double>(p->N, JP, &p->ks) : pick_set<float>(p->N, JP, &p->ks);
+    const bool naive = d.contraction == S3_CONTRACT_NAIVE;
+    const bool ok = (d.dtype == S3_F64) ? pick_set<double>(p->N, JP, &p->ks, naive)
+                                        : pick_set<float>(p->N, JP, &p->ks, naive);
     if (!ok) {
         delete p;
         return S3_ERR_UNSUPPORTED;

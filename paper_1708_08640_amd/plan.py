@@ -33,7 +33,7 @@ class S3Plan:
     def __init__(self, dims: Sequence[int], ranks: Sequence[int], matrices: Sequence[Tuple[int, int]] = (),
                  dtype: str = "f32", eta0: float = 0.01, mu: float = 0.1, lambda_reg: float = 0.01,
                  lambda_m: float = 10.0, batch: int = 65536, round_items: int = 65536, damping: bool = False,
-                 seed: int = 0, device: str = "cuda", hot_rows: int = 0):
+                 seed: int = 0, device: str = "cuda", hot_rows: int = 0, contraction: str = "reuse"):
         self.lib = load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -59,6 +59,9 @@ class S3Plan:
         d.round_items = int(round_items)
         d.seed = int(seed)
         d.hot_rows = int(hot_rows)
+        if contraction not in ("reuse", "naive"):
+            raise ValueError("contraction must be 'reuse' or 'naive'")
+        d.contraction = _abi.S3_CONTRACT_NAIVE if contraction == "naive" else _abi.S3_CONTRACT_REUSE
         self.desc = d
         h = C.c_void_p()
         check(self.lib.s3_plan_create(C.byref(d), C.byref(h)))
@@ -126,14 +129,15 @@ class S3Plan:
     @classmethod
     def from_problem(cls, problem, params, dtype: str = "f32", batch: int = 65536, order=None,
                      damping: bool = False, round_items: int = 65536, seed: int = 0, device: str = "cuda",
-                     hot_rows: int = 0, **hyper) -> "S3Plan":
+                     hot_rows: int = 0, contraction: str = "reuse", **hyper) -> "S3Plan":
         """Plan for a generated problem (see ``synth``) with initial (U, G, V)."""
         cfg = problem.cfg
         U, G, V = params
         kw = dict(eta0=cfg.eta0, mu=cfg.mu, lambda_reg=cfg.lambda_reg, lambda_m=cfg.lambda_m)
         kw.update(hyper)
         p = cls(cfg.dims, cfg.ranks, [(s.mode, s.cols) for s in cfg.matrices], dtype=dtype, batch=batch,
-                round_items=round_items, damping=damping, seed=seed, device=device, hot_rows=hot_rows, **kw)
+                round_items=round_items, damping=damping, seed=seed, device=device, hot_rows=hot_rows,
+                contraction=contraction, **kw)
         mats = [(problem.mat_row[m], problem.mat_col[m], problem.mat_val[m]) for m in range(len(problem.mat_val))]
         p.bind(problem.train_idx, problem.train_val, problem.test_idx, problem.test_val, mats, U, G, V, order)
         return p

@@ -17,7 +17,8 @@ def rounded_problem(p, dtype):
                                mat_val=[f(v) for v in p.mat_val])
 
 
-def setup(name, dtype="f64", batch=512, damping=False, order_seed=123, round_items=65536, **over):
+def setup(name, dtype="f64", batch=512, damping=False, order_seed=123, round_items=65536, contraction="reuse",
+          **over):
     from paper_1708_08640_amd import S3Plan
     cfg = get_config(name, **over)
     p = rounded_problem(make_problem(cfg), dtype)
@@ -27,7 +28,7 @@ def setup(name, dtype="f64", batch=512, damping=False, order_seed=123, round_ite
         U, G, V = [r(u) for u in U], r(G), [r(v) for v in V]
     order = item_order(p.n_items, order_seed, 0)
     plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=batch, order=order, damping=damping,
-                               round_items=round_items, seed=order_seed)
+                               round_items=round_items, seed=order_seed, contraction=contraction)
     ref = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices])
     return cfg, p, plan, ref, order
 

@@ -61,6 +61,8 @@ def _desc(_abi, **kw):
     (dict(eta0=-1.0), -1),
     (dict(n_mat=9), -1),
     (dict(mat_mode=(3, 0, 0, 0)), -1),
+    (dict(contraction=2), -1),
+    (dict(contraction=1, rank=(8, 8, 8)), -3),  # no naive kernels for J = 8
 ])
 def test_plan_create_rejects(kw, status):
     _abi, lib = _lib()

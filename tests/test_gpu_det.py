@@ -61,6 +61,19 @@ def test_det_epochs_match_oracle(name, dtype, batch, damping):
     compare_params(plan, ref, tol, f"after {n_ep} epochs")
 
 
+# the contraction without reuse (ablation kernels) computes the same batches
+@pytest.mark.parametrize("name,dtype,batch", [("cfg1", "f64", 500), ("tiny4", "f64", 7),
+                                              ("cfg2_slice", "f32", 4096)])
+def test_naive_contraction_matches_oracle(name, dtype, batch):
+    print(f"\n[det-naive] {name} {dtype} batch={batch}", flush=True)
+    cfg, p, plan, ref, order = setup(name, dtype, batch, True, contraction="naive")
+    eta = 0.01
+    for b in range(min(3, plan.n_batches())):
+        plan.det_batches(b, 1, eta)
+        oracle.minibatch_epoch(ref, p, order, batch, eta, b, 1, damping=True)
+        compare_params(plan, ref, TOL[dtype], f"batch {b}")
+
+
 def test_det_is_bitwise_reproducible():
     outs = []
     for _ in range(2):
