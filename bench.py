@@ -82,6 +82,45 @@ def cpu_baseline(cfg, p, U, G, V, sample, seed):
                       f"epoch order of the same workload ({dt:.1f} s)"}
 
 
+def scaling_sweep(args):
+    """The paper's data-scalability experiment on synthetic tensors: 3-way,
+    uniform indices, integer values 1..5, core 10^3, one coupled matrix on
+    mode 1 with a tenth as many entries; lock-free epochs at the benchmark's
+    round and hot-row settings."""
+    import torch
+    from paper_1708_08640_amd import S3Plan
+    from synth import init_params, make_problem
+    from synth.gen import UNIFORM15, Config, MatrixSpec
+    if args.scaling == "dims":
+        points = [(i, 1_000_000) for i in (1_000, 10_000, 100_000, 1_000_000, 10_000_000)]
+    else:
+        points = [(10_000, n) for n in (10_000, 100_000, 1_000_000, 10_000_000, 30_000_000)]
+    for I, nnz in points:
+        cfg = Config(name=f"uniform_I{I}_nnz{nnz}", dims=(I, I, I), ranks=(10, 10, 10), nnz=nnz,
+                     index_law=("uniform",) * 3, value_law=UNIFORM15,
+                     matrices=(MatrixSpec(mode=0, cols=I, nnz=max(nnz // 10, 1)),), dtype="f32",
+                     description=f"3-way {I}^3 uniform, {nnz} nnz, core 10^3, coupled {I}x{I} on mode 1")
+        log(f"scaling point I={I:,} nnz={nnz:,}: generating")
+        p = make_problem(cfg)
+        U, G, V = init_params(cfg)
+        plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", damping=True, round_items=args.round_items,
+                                   seed=args.seed, hot_rows=args.hot_rows)
+        for e in range(args.warmup):
+            plan.epoch(e, "lockfree")
+        torch.cuda.synchronize()
+        steps = max(args.steps, 2)
+        t0 = time.perf_counter()
+        for e in range(args.warmup, args.warmup + steps):
+            plan.epoch(e, "lockfree")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        print(json.dumps({"sweep": args.scaling, "I": I, "nnz_tensor_train": p.n_train,
+                          "nnz_matrix": p.n_items - p.n_train, "ms_per_epoch": ms,
+                          "updates_per_s": p.n_items / (ms / 1e3), "heldout_rmse": plan.rmse()}), flush=True)
+        del plan
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +136,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--scaling", choices=["dims", "nnz"], default=None,
+                    help="data-scalability sweep instead of the benchmark: epoch time of uniform 3-way tensors "
+                         "against the dimensionality I (1M entries) or the entry count (I = 10K); one JSON line "
+                         "per point")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), to calibrate the HBM "
                          "byte counters of a profiler run")
@@ -125,6 +168,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.scaling:
+        scaling_sweep(args)
+        return
     cfg = get_config(args.config)
     log(f"generating {cfg.name}: {cfg.description}")
     p = make_problem(cfg)
