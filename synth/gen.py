@@ -127,10 +127,12 @@ def _rng(seed: int, stream: int, sub: int = 0) -> np.random.Generator:
 
 
 @functools.lru_cache(maxsize=16)
+@functools.lru_cache(maxsize=8)
 def _zipf_cdf(I: int, s: float) -> np.ndarray:
     w = np.arange(1, I + 1, dtype=np.float64) ** (-float(s))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
+    cdf.setflags(write=False)  # shared by every draw of this law
     return cdf
 
 
@@ -179,7 +181,10 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 200) -
     total = int(strides[0]) * int(dims[0])
     if n > total:
         raise ValueError(f"{n} distinct entries requested from a space of {total}")
-    kept_keys = np.empty(0, dtype=np.int64)
+    # keys kept so far, as a few sorted runs: a round costs O(its own size x
+    # runs x log n) instead of a re-sort of everything kept
+    runs: List[np.ndarray] = []
+    n_kept = 0
     kept = []
     need = n
     for _ in range(max_rounds):
@@ -189,16 +194,23 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 200) -
         _, first = np.unique(keys, return_index=True)
         first.sort()
         c, keys = c[:, first], keys[first]
-        if kept_keys.size:
+        if runs:
             q = np.argsort(keys)
-            pos = np.empty(keys.size, dtype=np.int64)
-            pos[q] = np.searchsorted(kept_keys, keys[q])
-            pos = np.minimum(pos, kept_keys.size - 1)
-            fresh = kept_keys[pos] != keys
+            ks = keys[q]
+            seen = np.zeros(keys.size, dtype=bool)
+            for r in runs:
+                pos = np.minimum(np.searchsorted(r, ks), r.size - 1)
+                seen |= r[pos] == ks
+            fresh = np.empty(keys.size, dtype=bool)
+            fresh[q] = ~seen
             c, keys = c[:, fresh], keys[fresh]
         kept.append(c)
-        kept_keys = np.sort(np.concatenate([kept_keys, np.sort(keys)]), kind="stable")
-        need = n - kept_keys.size
+        n_kept += keys.size
+        if keys.size:
+            runs.append(np.sort(keys))
+        if len(runs) > 8:  # fold the small runs into one
+            runs = [runs[0], np.sort(np.concatenate(runs[1:]))]
+        need = n - n_kept
         if need == 0:
             return np.concatenate(kept, axis=1)
     raise RuntimeError("could not draw enough distinct coordinates")
