@@ -169,6 +169,10 @@ def _draw_values(rng, law, n):
     raise ValueError(f"unknown value law {law!r}")
 
 
+# set by make_problem(progress=True): a line per redraw round on stderr
+_progress = None
+
+
 def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 200) -> np.ndarray:
     """Draw n distinct coordinate tuples; draw(k) returns int64 [len(dims), k].
 
@@ -211,6 +215,8 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 200) -
         if len(runs) > 8:  # fold the small runs into one
             runs = [runs[0], np.sort(np.concatenate(runs[1:]))]
         need = n - n_kept
+        if _progress:
+            _progress(f"{n_kept:,} of {n:,} distinct coordinates")
         if need == 0:
             return np.concatenate(kept, axis=1)
     raise RuntimeError("could not draw enough distinct coordinates")
@@ -264,8 +270,20 @@ def _matrix(cfg: Config, m: int, spec: MatrixSpec, row_perm: np.ndarray):
     return coords[0].astype(np.int32), coords[1].astype(np.int32), vals
 
 
-def make_problem(cfg: Config) -> Problem:
-    """Draw the tensor, its train/test split and every coupled matrix."""
+def make_problem(cfg: Config, progress: bool = False) -> Problem:
+    """Draw the tensor, its train/test split and every coupled matrix.
+    progress: report each redraw round on stderr (large inputs)."""
+    global _progress
+    if progress:
+        import sys
+        _progress = lambda msg: print(f"[synth {cfg.name}] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    try:
+        return _make_problem(cfg)
+    finally:
+        _progress = None
+
+
+def _make_problem(cfg: Config) -> Problem:
     coords, vals, perms = _tensor(cfg)
     n = cfg.nnz
     n_test = int(round(cfg.test_frac * n))

@@ -38,7 +38,7 @@ def _gen(name):
     t = time.time()
     print(f"\n[large] generating {name}", flush=True)
     cfg = get_config(name)
-    p = rounded_problem(make_problem(cfg), "f32")
+    p = rounded_problem(make_problem(cfg, progress=True), "f32")
     r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
     U, G, V = init_params(cfg)
     print(f"[large] {cfg.description}: {p.n_train:,} train, {p.n_items - p.n_train:,} matrix entries "
@@ -75,6 +75,31 @@ def test_large_workload(name):
     # det: first batch against the oracle
     order = item_order(p.n_items, SEED, 0)
     plan = _plan(p, (U, G, V), order=order)
+    # adjoint (it runs on the det structures) with an upstream gradient on
+    # 2,000 sampled training entries, at the initial parameters
+    if name == "cfg3":
+        import torch
+        rng = np.random.default_rng(11)
+        sel = np.sort(rng.choice(p.n_train, 2000, replace=False))
+        gx = np.zeros(p.n_train)
+        gx[sel] = rng.standard_normal(sel.size)
+        gx = gx.astype(np.float32).astype(np.float64)
+        dU, dG, dV = plan.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"))
+        sub_idx = np.ascontiguousarray(p.train_idx[:, sel])
+        wU, wG, wV = oracle.adjoint(oracle.Params.from_arrays(U, G, V, modes), sub_idx, gx[sel], [], [])
+        for n in range(len(dU)):
+            d = dU[n].cpu().numpy().astype(np.float64)
+            rows = np.unique(sub_idx[n])
+            print(f"[large] adjoint U[{n}] rel {rel(d[rows], wU[n][rows]):.2e}", flush=True)
+            assert rel(d[rows], wU[n][rows]) <= 1e-5, f"adjoint U[{n}]"
+            mask = np.ones(d.shape[0], dtype=bool)
+            mask[rows] = False
+            assert not np.any(d[mask]), f"adjoint U[{n}] touched rows outside the sample"
+        assert rel(dG.cpu().numpy().astype(np.float64), wG) <= 1e-5, "adjoint G"
+        for m in range(len(dV)):
+            assert not np.any(dV[m].cpu().numpy()), f"adjoint V[{m}] without matrix gradients"
+        del dU, dG, dV
+
     eta = oracle.eta_at(cfg.eta0, cfg.mu, 0)
     plan.det_batches(0, 1, eta)
     gU, gG, gV = plan.params_numpy()
@@ -121,23 +146,3 @@ def test_large_workload(name):
     want = oracle.predict(oracle.Params.from_arrays(lU, lG, lV, modes), idx)
     assert rel(got, want) <= 1e-5
 
-    # adjoint with an upstream gradient on 2,000 sampled training entries
-    if name == "cfg3":
-        import torch
-        sel = np.sort(rng.choice(p.n_train, 2000, replace=False))
-        gx = np.zeros(p.n_train)
-        gx[sel] = rng.standard_normal(sel.size)
-        dU, dG, dV = plan.backward(torch.as_tensor(gx, dtype=torch.float32, device="cuda"))
-        sub_idx = np.ascontiguousarray(p.train_idx[:, sel])
-        params = oracle.Params.from_arrays(lU, lG, lV, modes)
-        wU, wG, wV = oracle.adjoint(params, sub_idx, gx[sel].astype(np.float32).astype(np.float64), [], [])
-        for n in range(len(dU)):
-            d = dU[n].cpu().numpy().astype(np.float64)
-            rows = np.unique(sub_idx[n])
-            assert rel(d[rows], wU[n][rows]) <= 1e-5, f"adjoint U[{n}]"
-            mask = np.ones(d.shape[0], dtype=bool)
-            mask[rows] = False
-            assert not np.any(d[mask]), f"adjoint U[{n}] touched rows outside the sample"
-        assert rel(dG.cpu().numpy().astype(np.float64), wG) <= 1e-5, "adjoint G"
-        for m in range(len(dV)):
-            assert not np.any(dV[m].cpu().numpy()), f"adjoint V[{m}] without matrix gradients"
