@@ -173,7 +173,7 @@ def _draw_values(rng, law, n):
 _progress = None
 
 
-def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 200) -> np.ndarray:
+def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) -> np.ndarray:
     """Draw n distinct coordinate tuples; draw(k) returns int64 [len(dims), k].
 
     Duplicates of an already-kept coordinate are discarded and redrawn, so the
