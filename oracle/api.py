@@ -26,7 +26,7 @@ class _Model(C.Structure):
         ("dims", C.c_int64 * MAXN), ("J", C.c_int32 * MAXN),
         ("U", _dp * MAXN), ("G", _dp),
         ("mode", C.c_int32 * MAXM), ("cols", C.c_int64 * MAXM),
-        ("V", _dp * MAXM),
+        ("V", _dp * MAXM), ("cp", C.c_int32),
     ]
 
 
@@ -113,19 +113,21 @@ def _ptr(a: np.ndarray, t):
 @dataclass
 class Params:
     """Model parameters in float64: U[n] (I_n x J_n), G (J_1 x .. x J_N, C order),
-    V[m] (K_m x J_{c_m}); ``modes[m]`` is the tensor mode matrix m couples to."""
+    V[m] (K_m x J_{c_m}); ``modes[m]`` is the tensor mode matrix m couples to.
+    cp: hyper-diagonal core (every J_n = J, G holds the J diagonal values)."""
     U: List[np.ndarray]
     G: np.ndarray
     V: List[np.ndarray]
     modes: List[int]
+    cp: bool = False
 
     @classmethod
-    def from_arrays(cls, U, G, V, modes):
+    def from_arrays(cls, U, G, V, modes, cp: bool = False):
         return cls([_f64(u).copy() for u in U], _f64(G).copy(), [_f64(v).copy() for v in V],
-                   [int(c) for c in modes])
+                   [int(c) for c in modes], bool(cp))
 
     def copy(self) -> "Params":
-        return Params.from_arrays(self.U, self.G, self.V, self.modes)
+        return Params.from_arrays(self.U, self.G, self.V, self.modes, self.cp)
 
     def _model(self) -> _Model:
         md = _Model()
@@ -136,7 +138,12 @@ class Params:
             md.dims[n] = u.shape[0]
             md.J[n] = u.shape[1]
             md.U[n] = _ptr(u, _dp)
-        assert tuple(self.G.shape) == tuple(u.shape[1] for u in self.U)
+        if self.cp:
+            J = self.U[0].shape[1]
+            assert all(u.shape[1] == J for u in self.U) and tuple(self.G.shape) == (J,)
+            md.cp = 1
+        else:
+            assert tuple(self.G.shape) == tuple(u.shape[1] for u in self.U)
         assert self.G.dtype == np.float64 and self.G.flags.c_contiguous
         md.G = _ptr(self.G, _dp)
         for m, v in enumerate(self.V):
@@ -349,6 +356,8 @@ def qr_orthogonalize(params: Params) -> Params:
     """Algorithm 1's closing step: U^(n) = Q R, U^(n) <- Q, G <- G x_n R, and for
     every coupled matrix on mode c, V <- V R^(c)T.  numpy's Householder QR serves
     as the factorisation primitive.  Returns a new Params."""
+    if params.cp:
+        raise ValueError("the QR step transforms the core densely; it does not apply to a hyper-diagonal core")
     out = params.copy()
     Rs = []
     for n, u in enumerate(params.U):

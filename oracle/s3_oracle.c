@@ -49,6 +49,10 @@ typedef struct {
     int32_t mode[OR_MAXM];
     int64_t cols[OR_MAXM];
     double *V[OR_MAXM];
+    int32_t cp;     /* 1: hyper-diagonal core (the CP special case of the
+                       model, Section 3's S^3CMTF-CP): every J_n equals J, G
+                       holds the J diagonal values g_r = G[r, .., r], and the
+                       core's other entries are structurally zero */
 } or_model;
 
 typedef struct {
@@ -78,16 +82,25 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 /* small helpers                                                        */
 
+/* number of stored core values: prod J_n, or J for a hyper-diagonal core */
 static int64_t core_size(const or_model *md)
 {
+    if (md->cp) return md->J[0];
     int64_t K = 1;
     for (int n = 0; n < md->N; ++n) K *= md->J[n];
     return K;
 }
 
-/* decode a flat row-major core index into (j_1..j_N) */
+/* decode a stored core index into its position (j_1..j_N) in the core: a
+ * row-major flat index, or for a hyper-diagonal core the position (r..r).
+ * Every sum over the core below runs over the stored values, so the CP
+ * model needs no other change: its entries off the diagonal are zero.      */
 static void decode(const or_model *md, int64_t flat, int32_t *jj)
 {
+    if (md->cp) {
+        for (int n = 0; n < md->N; ++n) jj[n] = (int32_t)flat;
+        return;
+    }
     for (int n = md->N - 1; n >= 0; --n) {
         jj[n] = (int32_t)(flat % md->J[n]);
         flat /= md->J[n];
@@ -446,6 +459,18 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
                         LU[n][rows[n]] += ww + reg_row[n];
                         pu *= uu;
                         off += md->J[n];
+                    }
+                    if (md->cp) {
+                        /* ||d x~ / d g||^2 over the diagonal only */
+                        pu = 0.0;
+                        for (int r = 0; r < md->J[0]; ++r) {
+                            double q = 1.0;
+                            for (int n = 0; n < N; ++n) {
+                                double v = urow(md, n, rows[n])[r];
+                                q *= v * v;
+                            }
+                            pu += q;
+                        }
                     }
                     LG += pu + reg_core;
                 }

@@ -379,3 +379,112 @@ def test_damped_step_of_one_entry():
         assert rel(b.U[n][rows[n]], params.U[n][rows[n]] - step * gU[n]) < 1e-13
     LG = np.prod([params.U[n][rows[n]] @ params.U[n][rows[n]] for n in range(3)]) + reg_core
     assert rel(b.G, params.G - eta / max(1.0, kappa * eta * LG) * gG) < 1e-13
+
+
+# ------------------------------------------------- CP (hyper-diagonal core)
+# The CP special case (Section 3's S^3CMTF-CP) stores only the J diagonal
+# values of the core.  Pins: the dense Kronecker model with the embedded
+# diagonal core, finite differences, and the Tucker oracle's own gradients
+# restricted to the diagonal.
+
+def _embed(g, N):
+    G = np.zeros((g.size,) * N)
+    for r in range(g.size):
+        G[(r,) * N] = g[r]
+    return G
+
+
+def _cp_params(rng, dims, J, mats, scale=0.7):
+    U = [rng.normal(0, scale, size=(I, J)) for I in dims]
+    g = rng.normal(0, scale, size=J)
+    V = [rng.normal(0, scale, size=(K, J)) for (_, K) in mats]
+    return oracle.Params.from_arrays(U, g, V, [c for c, _ in mats], cp=True)
+
+
+@pytest.mark.parametrize("dims,J", [((4, 3, 5), 2), ((3, 2, 2, 3), 2), ((5, 4, 3), 3)])
+def test_cp_predict_matches_dense_kronecker(dims, J):
+    rng = np.random.default_rng(40)
+    params = _cp_params(rng, dims, J, [])
+    grid = np.stack(np.meshgrid(*[np.arange(I) for I in dims], indexing="ij")).reshape(len(dims), -1)
+    got = oracle.predict(params, grid)
+    want = dense_predict(params.U, _embed(params.G, len(dims)), grid)
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("dims,J", [((4, 3, 5), 2), ((3, 2, 2, 3), 3)])
+def test_cp_item_grad_matches_fd(dims, J):
+    rng = np.random.default_rng(41)
+    params = _cp_params(rng, dims, J, [])
+    N = len(dims)
+    rows = [int(rng.integers(0, I)) for I in dims]
+    x, reg_row, reg_core = 2.5, [0.03 * (n + 1) for n in range(N)], 0.07
+    e, gU, gg = oracle.tensor_item_grad(params, rows, x, reg_row, reg_core)
+
+    def phi():
+        return item_phi(params.U, _embed(params.G, N), rows, x, reg_row, reg_core)
+
+    for n in range(N):
+        mask = np.zeros_like(params.U[n], dtype=bool)
+        mask[rows[n]] = True
+        fd = fd_grad(phi, params.U[n], mask=mask)[rows[n]]
+        assert rel(gU[n], fd) < 1e-7
+    assert rel(gg, fd_grad(phi, params.G)) < 1e-7
+    assert abs(e - (x - dense_predict(params.U, _embed(params.G, N), np.array(rows)[:, None])[0])) < 1e-12
+
+
+def test_cp_grads_are_the_tucker_grads_on_the_diagonal():
+    rng = np.random.default_rng(42)
+    cp = _cp_params(rng, (6, 5, 4), 3, [])
+    tk = oracle.Params.from_arrays(cp.U, _embed(cp.G, 3), cp.V, cp.modes)
+    rows, x, reg_row, reg_core = [2, 4, 1], 3.0, [0.1, 0.2, 0.3], 0.05
+    e1, gU1, gg = oracle.tensor_item_grad(cp, rows, x, reg_row, reg_core)
+    e2, gU2, gG = oracle.tensor_item_grad(tk, rows, x, reg_row, reg_core)
+    assert abs(e1 - e2) < 1e-14
+    for a, b in zip(gU1, gU2):
+        assert rel(a, b) < 1e-14
+    assert rel(gg, [gG[r, r, r] for r in range(3)]) < 1e-14
+
+
+def _cp_problem(name, **kw):
+    cfg = get_config(name, **kw)
+    p = make_problem(cfg)
+    U, G, V = init_params(cfg)
+    g = np.array([G[(r,) * cfg.order] for r in range(cfg.ranks[0])])
+    return cfg, p, oracle.Params.from_arrays(U, g, V, [s.mode for s in cfg.matrices], cp=True)
+
+
+def test_cp_batch_of_one_is_sgd():
+    cfg, p, params = _cp_problem("cfg1")
+    order = item_order(p.n_items, 5, 0)
+    a, b = params.copy(), params.copy()
+    oracle.sgd_epoch(a, p, order, 0.01)
+    oracle.minibatch_epoch(b, p, order, 1, 0.01, damping=True)
+    for x, y in zip(a.U + [a.G] + a.V, b.U + [b.G] + b.V):
+        assert np.array_equal(x, y)
+    assert rel(a.G, params.G) > 0  # the core moved
+
+
+def test_cp_damped_step_of_one_entry():
+    cfg, p, params = _cp_problem("tiny3", matrices=(), nnz=12, dims=(10, 8, 9), ranks=(2, 2, 2))
+    cnt, _ = oracle.counts(params, p)
+    rows = [int(p.train_idx[n][0]) for n in range(3)]
+    reg_row = [cfg.lambda_reg / cnt[n][rows[n]] for n in range(3)]
+    reg_core = cfg.lambda_reg / p.n_train
+    eta = 50.0
+    e, gU, gg = oracle.tensor_item_grad(params, rows, p.train_val[0], reg_row, reg_core)
+    b = params.copy()
+    oracle.minibatch_epoch(b, p, np.arange(p.n_items), 1, eta, 0, 1, damping=True)
+    u = [params.U[n][rows[n]] for n in range(3)]
+    # curvature of x~ in the diagonal core values: sum_r prod_n u_n[r]^2
+    LG = sum(np.prod([u[n][r] ** 2 for n in range(3)]) for r in range(2)) + reg_core
+    assert rel(b.G, params.G - eta / max(1.0, 4.0 * eta * LG) * gg) < 1e-13
+    for n in range(3):
+        w = params.G * np.prod([u[m] for m in range(3) if m != n], axis=0)
+        step = eta / max(1.0, 4.0 * eta * (w @ w + reg_row[n]))
+        assert rel(b.U[n][rows[n]], u[n] - step * gU[n]) < 1e-13
+
+
+def test_cp_qr_is_rejected():
+    rng = np.random.default_rng(43)
+    with pytest.raises(ValueError):
+        oracle.qr_orthogonalize(_cp_params(rng, (5, 4, 3), 2, []))
