@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tensor+matrix nonzero updates/sec per epoch at fixed held-out RMSE, 1 GPU"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 
 
 def log(msg):
@@ -87,6 +88,7 @@ def scaling_sweep(args):
     uniform indices, integer values 1..5, core 10^3, one coupled matrix on
     mode 1 with a tenth as many entries; lock-free epochs at the benchmark's
     round and hot-row settings."""
+    import numpy as np
     import torch
     from paper_1708_08640_amd import S3Plan
     from synth import init_params, make_problem
@@ -131,6 +133,8 @@ def main():
     ap.add_argument("--round-items", type=int, default=524288)
     ap.add_argument("--hot-rows", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--core", default="tucker", choices=["tucker", "cp"],
+                    help="cp: the hyper-diagonal core (the CP special case), judged against the HBM roof")
     ap.add_argument("--contraction", default="reuse", choices=["reuse", "naive"],
                     help="naive: the per-entry contraction without reuse of partial products (ablation)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
@@ -150,6 +154,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -175,12 +180,14 @@ def main():
     log(f"generating {cfg.name}: {cfg.description}")
     p = make_problem(cfg)
     U, G, V = init_params(cfg)
+    if args.core == "cp":  # the hyper-diagonal part of the same seeded core
+        G = np.array([G[(r,) * cfg.order] for r in range(cfg.ranks[0])])
     n_updates = p.n_items
     log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {n_updates - p.n_train:,} matrix entries")
     order = item_order(p.n_items, args.seed, 0) if args.mode == "det" else None
     plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", batch=args.batch, order=order, damping=True,
                                round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows,
-                               contraction=args.contraction)
+                               contraction=args.contraction, core=args.core)
     torch.cuda.synchronize()
     rmse0 = plan.rmse()
     log(f"bound; initial held-out RMSE {rmse0:.4f}")
@@ -235,6 +242,18 @@ def main():
         "avg_launch_ms": kernel_ms / max(launches, 1), "kernel_share_of_epoch": kernel_ms / (t1 - t0) / 1e3,
     }
 
+    if args.core == "cp":
+        # CP: O(NJ) flops per entry, so the bound is HBM: algorithmic bytes =
+        # index + value stream and every touched row read and written once
+        J = cfg.ranks[0]
+        t_bytes = 4 * cfg.order + 4 + 2 * 4 * J * cfg.order
+        m_bytes = 12 + 2 * 2 * 4 * J
+        nbytes = (t_bytes * p.n_train + (m_bytes * (n_updates - p.n_train) if args.mode == "lockfree" else 0)) * \
+            args.steps
+        gbs = nbytes / (kernel_ms / 1e3) / 1e9 if kernel_ms > 0 else None
+        roofline.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": (gbs / PEAK_HBM_GBS) if gbs else None, "traffic": None,
+                         "bytes_per_tensor_entry": t_bytes, "bytes_per_matrix_entry": m_bytes})
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on {args.cpu_sample:,} items (CPU baseline)")
@@ -249,7 +268,7 @@ def main():
                    "round_items": args.round_items if args.mode == "lockfree" else None,
                    "hot_rows": args.hot_rows if args.mode == "lockfree" else None,
                    "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
-                   "contraction": args.contraction,
+                   "contraction": args.contraction, "core": args.core,
                    "updates_per_epoch": n_updates, "parallelism": "single GPU"},
         "heldout_rmse": rmse, "heldout_rmse_init": rmse0, "rmse_epochs": E, "rmse_target": target,
         "rmse_ok": (rmse <= target) if target is not None else None,

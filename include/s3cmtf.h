@@ -100,6 +100,13 @@ enum { S3_DAMP_NONE = 0, S3_DAMP_CURVATURE = 1 };       /* s3_desc.damping */
 #define S3_CONTRACT_REUSE 0
 #define S3_CONTRACT_NAIVE 1
 
+/* Core structure (s3_desc.core_kind). */
+#define S3_CORE_TUCKER 0   /* dense core J_1 x ... x J_N (Eq 4)             */
+#define S3_CORE_CP 1       /* hyper-diagonal core (the CP special case of
+                              Section 3): every J_n equals J and G holds the
+                              J diagonal values; s3_orthogonalize does not
+                              apply                                          */
+
 typedef struct {
     int32_t order;                       /* N: 3 or 4                        */
     int32_t n_mat;                       /* M: 0..S3_MAX_MATRICES            */
@@ -124,6 +131,10 @@ typedef struct {
                                             ablation of Lemma 4; N = 3 with
                                             J <= 4 or J = 10, N = 4 with J <= 2,
                                             else S3_ERR_UNSUPPORTED)          */
+    int32_t core_kind;                   /* S3_CORE_TUCKER (default) or
+                                            S3_CORE_CP (then every rank must be
+                                            equal, else S3_ERR_INVALID_ARG, and
+                                            contraction must be REUSE)        */
 } s3_desc;
 
 /* Device buffers handed to s3_bind.  Values and parameters are `double` for

@@ -23,6 +23,7 @@ S3_F64, S3_F32, S3_BF16 = 0, 1, 2
 S3_DET_MINIBATCH, S3_LOCKFREE = 0, 1
 S3_DAMP_NONE, S3_DAMP_CURVATURE = 0, 1
 S3_CONTRACT_REUSE, S3_CONTRACT_NAIVE = 0, 1
+S3_CORE_TUCKER, S3_CORE_CP = 0, 1
 
 # every function the header declares
 EXPORTS = [
@@ -41,7 +42,7 @@ class S3Desc(C.Structure):
         ("dtype", C.c_int32), ("damping", C.c_int32),
         ("eta0", C.c_double), ("mu", C.c_double), ("lambda_reg", C.c_double), ("lambda_m", C.c_double),
         ("batch", C.c_int64), ("round_items", C.c_int64), ("seed", C.c_uint64),
-        ("hot_rows", C.c_int32), ("contraction", C.c_int32),
+        ("hot_rows", C.c_int32), ("contraction", C.c_int32), ("core_kind", C.c_int32),
     ]
 
 

@@ -170,4 +170,80 @@ S3_DEV T predict(GP G, const T (&u)[N][JP]) {
     return acc;
 }
 
+// CP special case (hyper-diagonal core, Section 3's S^3CMTF-CP): g holds
+// the JP diagonal values (zero padded), x~ = sum_r g_r prod_n u_n[r] and
+// w_n[r] = g_r prod_{m != n} u_m[r]: O(N^2 J) per entry.
+template <int N, int JP, typename T, typename GP>
+S3_DEV void contract_cp(GP g, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {
+    T x = T(0);
+#pragma unroll
+    for (int r = 0; r < JP; ++r) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            T p = g[r];
+#pragma unroll
+            for (int m = 0; m < N; ++m)
+                if (m != n) p *= u[m][r];
+            w[n][r] = p;
+        }
+        x = fmaT(w[0][r], u[0][r], x);
+    }
+    xhat = x;
+}
+
+template <int N, int JP, typename T, typename GP> S3_DEV T predict_cp(GP g, const T (&u)[N][JP]) {
+    T x = T(0);
+#pragma unroll
+    for (int r = 0; r < JP; ++r) {
+        T p = g[r];
+#pragma unroll
+        for (int n = 0; n < N; ++n) p *= u[n][r];
+        x += p;
+    }
+    return x;
+}
+
+// contraction kinds of the per-entry kernels
+constexpr int kReuse = 0;  // single pass with reuse (above)
+constexpr int kNaive = 1;  // ablation: no reuse
+constexpr int kCP = 2;     // hyper-diagonal core
+
+template <int CT, int N, int JP, typename T, typename GP>
+S3_DEV void contract_any(GP G, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {
+    if constexpr (CT == kCP) contract_cp<N, JP, T>(G, u, w, xhat);
+    else if constexpr (CT == kNaive) contract_naive<N, JP, T>(G, u, w, xhat);
+    else contract<N, JP, T>(G, u, w, xhat);
+}
+
+template <int CT, int N, int JP, typename T, typename GP> S3_DEV T predict_any(GP G, const T (&u)[N][JP]) {
+    if constexpr (CT == kCP) return predict_cp<N, JP, T>(G, u);
+    else return predict<N, JP, T>(G, u);
+}
+
+// curvature of x~ in the core values: prod_n |u_n|^2 (the squared norm of
+// u^(1) o ... o u^(N)), or for a hyper-diagonal core sum_r prod_n u_n[r]^2
+template <int CT, int N, int JP, typename T> S3_DEV T core_curv(const T (&u)[N][JP]) {
+    if constexpr (CT == kCP) {
+        T s = T(0);
+#pragma unroll
+        for (int r = 0; r < JP; ++r) {
+            T p = T(1);
+#pragma unroll
+            for (int n = 0; n < N; ++n) p *= u[n][r] * u[n][r];
+            s += p;
+        }
+        return s;
+    } else {
+        T p = T(1);
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            T uu = T(0);
+#pragma unroll
+            for (int k = 0; k < JP; ++k) uu = fmaT(u[n][k], u[n][k], uu);
+            p *= uu;
+        }
+        return p;
+    }
+}
+
 }  // namespace s3

@@ -229,7 +229,7 @@ S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t 
 // regulariser).  The mode is a template flag and the entry's value is loaded
 // before the contraction: with a run-time choice between two loads after it
 // the compiler front-loads every scalar core load and spills them.
-template <int N, int JP, typename T, bool ADJ, bool NAIVE = false>
+template <int N, int JP, typename T, bool ADJ, int CT = kReuse>
 __global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32_t *__restrict__ ids,
                                                     int64_t nt, const T *__restrict__ Gp,
                                                     T *__restrict__ scr, int64_t stride,
@@ -242,29 +242,25 @@ __global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32
         load_rows<N, JP, T>(A, e, u, rows);
         const T xv = ADJ ? gx[e] : A.val[e];
         T xhat;
-        if constexpr (NAIVE) contract_naive<N, JP, T>(Gp, u, w, xhat);
-        else contract<N, JP, T>(Gp, u, w, xhat);
+        contract_any<CT, N, JP, T>(Gp, u, w, xhat);
         constexpr bool train = !ADJ;
         const T q = train ? -(xv - xhat) : xv;
         // fixed JP stride per mode (padding lanes hold zeros): stores at
         // run-time offsets here also make the compiler spill the core loads
         T *out = scr + s * stride;
-        T LG = T(1);
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const T reg = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
-            T ww = T(0), uu = T(0);
+            T ww = T(0);
 #pragma unroll
             for (int k = 0; k < JP; ++k) {
                 out[n * JP + k] = fmaT(q, w[n][k], reg * u[n][k]);
                 ww = fmaT(w[n][k], w[n][k], ww);
-                uu = fmaT(u[n][k], u[n][k], uu);
             }
             out[N * JP + n] = ww + reg;
-            LG *= uu;
         }
         out[stride - 2] = q;
-        out[stride - 1] = LG;
+        out[stride - 1] = core_curv<CT, N, JP, T>(u);
     }
 }
 
@@ -473,6 +469,48 @@ __global__ __launch_bounds__(kChunk) void k_core_partial_mfma(TensorArgs<float> 
     }
 }
 
+// Det-mode core partial of one chunk for a hyper-diagonal core: lane t
+// holds q_t prod_n u_n[r] for every r (and the entry's core curvature); the
+// chunk sums go through the wavefronts in order.
+template <int N, int JP, typename T>
+__global__ __launch_bounds__(kChunk) void k_core_partial_cp(TensorArgs<T> A, const int32_t *__restrict__ ids,
+                                                            int64_t nt, const T *__restrict__ scr, int64_t stride,
+                                                            T *__restrict__ part, T *__restrict__ part_curv) {
+    __shared__ T s_red[kChunk / kWave][JP + 1];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t s = (int64_t)blockIdx.x * kChunk + tid;
+    T c[JP + 1];
+#pragma unroll
+    for (int r = 0; r <= JP; ++r) c[r] = T(0);
+    if (s < nt) {
+        const int64_t e = ids[s];
+        T u[N][JP];
+        int32_t rows[N];
+        load_rows<N, JP, T>(A, e, u, rows);
+        const T q = scr[s * stride + stride - 2];
+#pragma unroll
+        for (int r = 0; r < JP; ++r) {
+            T p = q;
+#pragma unroll
+            for (int n = 0; n < N; ++n) p *= u[n][r];
+            c[r] = p;
+        }
+        c[JP] = scr[s * stride + stride - 1];
+    }
+#pragma unroll
+    for (int r = 0; r <= JP; ++r) {
+        const T t = wave_sum(c[r]);
+        if (lane == 0) s_red[wv][r] = t;
+    }
+    __syncthreads();
+    if (tid <= JP) {
+        T t = T(0);
+        for (int w = 0; w < kChunk / kWave; ++w) t += s_red[w][tid];
+        if (tid < JP) part[(int64_t)blockIdx.x * JP + tid] = t;
+        else part_curv[blockIdx.x] = t;
+    }
+}
+
 // G[j] -= eta * step, step = (sum_chunks P + nt * reg_core * G) / damp;
 // accumulate != 0: dG[j] += sum_chunks P (adjoint).  One block per 16 padded
 // core elements: lane el of phase ph sums chunks ph, ph + 16, ... of element
@@ -481,11 +519,11 @@ template <int N, typename T>
 __global__ __launch_bounds__(256) void k_core_apply(T *__restrict__ G, const T *__restrict__ part,
                                                     const T *__restrict__ part_curv, int64_t nchunks, int JP,
                                                     int J0, int J1, int J2, int J3, int64_t nt, T reg_core,
-                                                    T eta, T kappa, int damp, int accumulate) {
+                                                    T eta, T kappa, int damp, int accumulate, int cp) {
     __shared__ T s_p[2][16][17];
     const int Js[4] = {J0, J1, J2, J3};
     int64_t KP = 1;
-    for (int n = 0; n < N; ++n) KP *= JP;
+    for (int n = 0; n < (cp ? 1 : N); ++n) KP *= JP;
     const int el = threadIdx.x & 15, ph = threadIdx.x >> 4;
     const int64_t pj = (int64_t)blockIdx.x * 16 + el;
     const int64_t pr = pj < KP ? pj : 0;
@@ -510,9 +548,10 @@ __global__ __launch_bounds__(256) void k_core_apply(T *__restrict__ G, const T *
         s += s_p[0][q][el];
         L += s_p[1][q][el];
     }
-    // padded index -> core index (the padding has no element)
+    // padded index -> core index (the padding has no element); a
+    // hyper-diagonal core is one padded vector
     int64_t rem = pj, j = 0, mul = 1;
-    for (int n = N - 1; n >= 0; --n) {
+    for (int n = (cp ? 0 : N - 1); n >= 0; --n) {
         const int jn = (int)(rem % JP);
         rem /= JP;
         if (jn >= Js[n]) return;
@@ -671,7 +710,7 @@ __global__ void k_long_write(const int32_t *__restrict__ flag, const int32_t *__
 
 // sum over entries of (x - x~)^2: one entry per thread, one double partial
 // per block (the host adds the partials in block order: deterministic)
-template <int N, int JP, typename T>
+template <int N, int JP, typename T, int CT = kReuse>
 __global__ __launch_bounds__(256) void k_sq_err_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
                                                        double *__restrict__ part) {
     __shared__ double s[256];
@@ -681,7 +720,7 @@ __global__ __launch_bounds__(256) void k_sq_err_tensor(TensorArgs<T> A, const T 
         T u[N][JP];
         int32_t rows[N];
         load_rows<N, JP, T>(A, e, u, rows);
-        const T r = A.val[e] - predict<N, JP, T>(Gp, u);
+        const T r = A.val[e] - predict_any<CT, N, JP, T>(Gp, u);
         acc = (double)r * (double)r;
     }
     s[threadIdx.x] = acc;
@@ -693,7 +732,7 @@ __global__ __launch_bounds__(256) void k_sq_err_tensor(TensorArgs<T> A, const T 
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-template <int N, int JP, typename T>
+template <int N, int JP, typename T, int CT = kReuse>
 __global__ __launch_bounds__(256) void k_predict(TensorArgs<T> A, const T *__restrict__ Gp,
                                                  T *__restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -701,7 +740,7 @@ __global__ __launch_bounds__(256) void k_predict(TensorArgs<T> A, const T *__res
         T u[N][JP];
         int32_t rows[N];
         load_rows<N, JP, T>(A, e, u, rows);
-        out[e] = predict<N, JP, T>(Gp, u);
+        out[e] = predict_any<CT, N, JP, T>(Gp, u);
     }
 }
 

@@ -268,14 +268,16 @@ S3_DEV void lf_matrix_tile(const LFMatArgs<T> &Y, int m, int64_t blk, const LFAr
 // minimum waves per SIMD requested from the register allocator: 3 for cores
 // of up to 1,024 entries (fits in 168 VGPRs without spilling, and matches the
 // three 256-thread workgroups per CU the LDS allows), 1 otherwise
-template <int N, int JP> constexpr int lf_min_waves() { return ((N == 3 ? JP * JP * JP : JP * JP * JP * JP) <= 1024) ? 3 : 1; }
+template <int N, int JP, int CT = kReuse> constexpr int lf_min_waves() {
+    return (CT == kCP || (N == 3 ? JP * JP * JP : JP * JP * JP * JP) <= 1024) ? 3 : 1;
+}
 
-template <int N, int JP, typename T, bool EXACT, bool NAIVE = false>
-__global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
+template <int N, int JP, typename T, bool EXACT, int CT = kReuse>
+__global__ __launch_bounds__(kTile, (lf_min_waves<N, JP, CT>())) void k_lf_tensor(TensorArgs<T> A, const T *__restrict__ Gp,
                                                                           LFArgs<T> L, LFMatArgs<T> Y,
                                                                           int64_t n_tensor, T eta, T kappa) {
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
-    constexpr int KP = JP * TAIL;
+    constexpr int KP = (CT == kCP) ? JP : JP * TAIL;  // stored core values (padded)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if ((int64_t)blockIdx.x >= n_tensor) {
         int64_t blk = (int64_t)blockIdx.x - n_tensor;
@@ -314,8 +316,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
 #pragma unroll
         for (int n = 0; n < N; ++n) regs[n] = L.meta_reg[(int64_t)n * A.nnz + e];
         T xhat;
-        if constexpr (NAIVE) contract_naive<N, JP, T>(Gp, u, w, xhat);
-        else contract<N, JP, T>(Gp, u, w, xhat);
+        contract_any<CT, N, JP, T>(Gp, u, w, xhat);
         q = -(xv - xhat);
         LG = T(1);
 #pragma unroll
@@ -344,6 +345,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
                     if (EXACT || k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
             }
         }
+        if constexpr (CT == kCP) LG = core_curv<kCP, N, JP, T>(u);
     }
     {
         const T lg = wave_sum(LG);
@@ -356,6 +358,35 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
     __syncthreads();
     lf_chunk_pass<JP, N>(s_stage, s_tab, L.chunks + (size_t)tile * N * kTile, L.nchunks + tile * N, L.H);
     __syncthreads();
+    T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
+    if constexpr (CT == kCP) {
+        // hyper-diagonal core: lane sums of q prod_n u_n[r], added over the
+        // wavefronts in order (the sorted rows are consumed, so s_stage is free)
+        T *s_red = s_stage;  // [NWV][JP]
+        T c[JP];
+#pragma unroll
+        for (int r = 0; r < JP; ++r) c[r] = T(0);
+        if (live) {
+#pragma unroll
+            for (int r = 0; r < JP; ++r) {
+                T p = q;
+#pragma unroll
+                for (int n = 0; n < N; ++n) p *= u[n][r];
+                c[r] = p;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < JP; ++r) {
+            const T t = wave_sum(c[r]);
+            if ((tid & (kWave - 1)) == 0) s_red[(tid / kWave) * JP + r] = t;
+        }
+        __syncthreads();
+        if (tid < JP) {
+            T t = T(0);
+            for (int w = 0; w < NWV; ++w) t += s_red[w * JP + tid];
+            core[tid] = t;
+        }
+    } else {
     // stage the core-gradient operands (over the sorted rows, now consumed)
     if (live) {
 #pragma unroll
@@ -373,7 +404,6 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
             for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = T(0);
     }
     __syncthreads();
-    T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
     if constexpr (std::is_same<T, float>::value) {
         core_tile_mfma<N, JP>(s_q, s_u, core);
     } else {
@@ -401,6 +431,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP>())) void k_lf_tensor(Te
             for (int k = 0; k < JS; ++k) core[(size_t)(j0 + k) * TAIL + tau] = acc[k];
         }
     }
+    }  // Tucker core
     if (tid == 0) {
         T lg = T(0), cnt = T(0);
         for (int w = 0; w < NWV; ++w) {
@@ -433,7 +464,8 @@ struct LFApplyArgs {
     const void *tab_m[kMaxM];               // matrix tables [nwg_m][2][H][JP+1]
     int64_t nwg_m[kMaxM];
     const void *core_t;                     // tensor core partials [nwg_t][KP+2]
-    int64_t KP;                             // padded core size JP^N
+    int64_t KP;                             // padded core size JP^N (JP: hyper-diagonal)
+    int cp;                                 // hyper-diagonal core
 };
 
 constexpr int kApplyThreads = 256;
@@ -554,7 +586,7 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
     // padded index -> core index (skip the zero padding)
     const int Js[4] = {J0, J1, J2, J3};
     int64_t rem = jp, j = 0, mul = 1;
-    for (int n = N - 1; n >= 0; --n) {
+    for (int n = (a.cp ? 0 : N - 1); n >= 0; --n) {
         const int jn = (int)(rem % JP);
         rem /= JP;
         if (jn >= Js[n]) return;
@@ -762,6 +794,7 @@ s3_status lockfree_build(LockFreeState &s, const s3_desc &d, const s3_buffers *b
     s.apply.tab_t = s.tab_t;
     s.apply.core_t = s.core_t;
     s.apply.KP = s.KP;
+    s.apply.cp = d.core_kind == S3_CORE_CP;
     // per-entry metadata streams
     LFMetaSrc src{};
     for (int g = 0; g < N + M; ++g) src.hot_slot[g] = s.hot_slot[g];
@@ -809,7 +842,7 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
     return L;
 }
 
-template <int N, int JP, typename T, bool EXACT, bool NAIVE = false>
+template <int N, int JP, typename T, bool EXACT, int CT = kReuse>
 void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
                             T eta, hipStream_t st) {
     LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
@@ -844,7 +877,7 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
     const size_t W = (size_t)JP + 1;
     const size_t smem = std::max((size_t)N * (s.H * W + kTile * W) + 2 * (kTile / kWave),
                                  (size_t)2 * (s.H * W + kTile * W)) * sizeof(T);
-    hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT, NAIVE>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
+    hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
                        count, eta, (T)(N + 1));
 }
 

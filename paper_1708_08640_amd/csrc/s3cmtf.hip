@@ -153,16 +153,16 @@ template <typename T> TensorArgs<T> tensor_args(const s3_plan *p, const int32_t 
     return a;
 }
 
-// NAIVE: the contraction without reuse (ablation); it changes only the
-// per-entry training kernels
-template <int N, int JP, typename T, bool NAIVE = false> struct Impl {
+// CT: the per-entry contraction (reuse, naive ablation, or the
+// hyper-diagonal CP core)
+template <int N, int JP, typename T, int CT = kReuse> struct Impl {
     static void det_tensor(s3_plan *p, const int32_t *ids, int64_t nt, const void *gx, hipStream_t st) {
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
         if (gx)
-            hipLaunchKernelGGL((k_det_tensor<N, JP, T, true, NAIVE>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256),
+            hipLaunchKernelGGL((k_det_tensor<N, JP, T, true, CT>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256),
                                0, st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
         else
-            hipLaunchKernelGGL((k_det_tensor<N, JP, T, false, NAIVE>), dim3(grid_for(nt, 256, 1ll << 30)),
+            hipLaunchKernelGGL((k_det_tensor<N, JP, T, false, CT>), dim3(grid_for(nt, 256, 1ll << 30)),
                                dim3(256), 0, st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride,
                                (const T *)nullptr);
     }
@@ -171,7 +171,10 @@ template <int N, int JP, typename T, bool NAIVE = false> struct Impl {
         constexpr int TPB = ((TAIL + 63) / 64) * 64;
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
         const int64_t nch = (nt + kChunk - 1) / kChunk;
-        if constexpr (std::is_same<T, float>::value)
+        if constexpr (CT == kCP)
+            hipLaunchKernelGGL((k_core_partial_cp<N, JP, T>), dim3((unsigned)nch), dim3(kChunk), 0, st, a, ids, nt,
+                               (const T *)p->scr, p->t_stride, (T *)p->part, (T *)p->part_curv);
+        else if constexpr (std::is_same<T, float>::value)
             hipLaunchKernelGGL((k_core_partial_mfma<N, JP>), dim3((unsigned)nch), dim3(kChunk), 0, st, a, ids, nt,
                                (const float *)p->scr, p->t_stride, (float *)p->part, (float *)p->part_curv);
         else
@@ -181,40 +184,61 @@ template <int N, int JP, typename T, bool NAIVE = false> struct Impl {
     static void sq_err(s3_plan *p, const int32_t *idx, const void *val, int64_t nnz, double *part,
                        hipStream_t st) {
         auto a = tensor_args<T>(p, idx, val, nnz);
-        hipLaunchKernelGGL((k_sq_err_tensor<N, JP, T>), dim3(sq_blocks(nnz)), dim3(256), 0, st, a,
+        hipLaunchKernelGGL((k_sq_err_tensor<N, JP, T, CT>), dim3(sq_blocks(nnz)), dim3(256), 0, st, a,
                            (const T *)p->Gp, part);
     }
     static void predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *out, hipStream_t st) {
         auto a = tensor_args<T>(p, idx, nullptr, nnz);
-        hipLaunchKernelGGL((k_predict<N, JP, T>), dim3(grid_for(nnz, 256, 1ll << 30)), dim3(256), 0, st, a,
+        hipLaunchKernelGGL((k_predict<N, JP, T, CT>), dim3(grid_for(nnz, 256, 1ll << 30)), dim3(256), 0, st, a,
                            (const T *)p->Gp, (T *)out);
     }
     static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st) {
         if (p->exact)
-            lockfree_tensor_launch<N, JP, T, true, NAIVE>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+            lockfree_tensor_launch<N, JP, T, true, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
                                                           (const T *)p->Gp, first, count, (T)eta, st);
         else
-            lockfree_tensor_launch<N, JP, T, false, NAIVE>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+            lockfree_tensor_launch<N, JP, T, false, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
                                                            (const T *)p->Gp, first, count, (T)eta, st);
     }
 };
 
-template <int N, int JP, typename T, bool NAIVE = false> KernelSet make_set() {
-    using I = Impl<N, JP, T, NAIVE>;
+template <int N, int JP, typename T, int CT = kReuse> KernelSet make_set() {
+    using I = Impl<N, JP, T, CT>;
     return KernelSet{&I::det_tensor, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor};
 }
 
 // the ablation's kernels exist for the shapes of the tests and of the
 // 10M-entry workload only
 template <typename T> bool pick_naive_set(int N, int JP, KernelSet *ks) {
-    if (N == 3 && JP == 3) { *ks = make_set<3, 3, T, true>(); return true; }
-    if (N == 3 && JP == 4) { *ks = make_set<3, 4, T, true>(); return true; }
-    if (N == 3 && JP == 10) { *ks = make_set<3, 10, T, true>(); return true; }
-    if (N == 4 && JP == 2) { *ks = make_set<4, 2, T, true>(); return true; }
+    if (N == 3 && JP == 3) { *ks = make_set<3, 3, T, kNaive>(); return true; }
+    if (N == 3 && JP == 4) { *ks = make_set<3, 4, T, kNaive>(); return true; }
+    if (N == 3 && JP == 10) { *ks = make_set<3, 10, T, kNaive>(); return true; }
+    if (N == 4 && JP == 2) { *ks = make_set<4, 2, T, kNaive>(); return true; }
     return false;
 }
 
-template <typename T> bool pick_set(int N, int JP, KernelSet *ks, bool naive) {
+template <typename T> bool pick_cp_set(int N, int JP, KernelSet *ks) {
+    if (N == 3) {
+        switch (JP) {
+        case 3: *ks = make_set<3, 3, T, kCP>(); return true;
+        case 4: *ks = make_set<3, 4, T, kCP>(); return true;
+        case 8: *ks = make_set<3, 8, T, kCP>(); return true;
+        case 10: *ks = make_set<3, 10, T, kCP>(); return true;
+        case 12: *ks = make_set<3, 12, T, kCP>(); return true;
+        case 16: *ks = make_set<3, 16, T, kCP>(); return true;
+        }
+    } else if (N == 4) {
+        switch (JP) {
+        case 2: *ks = make_set<4, 2, T, kCP>(); return true;
+        case 4: *ks = make_set<4, 4, T, kCP>(); return true;
+        case 8: *ks = make_set<4, 8, T, kCP>(); return true;
+        }
+    }
+    return false;
+}
+
+template <typename T> bool pick_set(int N, int JP, KernelSet *ks, bool naive, bool cp) {
+    if (cp) return pick_cp_set<T>(N, JP, ks);
     if (naive) return pick_naive_set<T>(N, JP, ks);
     if (N == 3) {
         switch (JP) {
@@ -285,13 +309,15 @@ void core_apply(s3_plan *p, int64_t nt, double eta, int acc, void *dst, hipStrea
     auto kern = (p->N == 3) ? k_core_apply<3, T> : k_core_apply<4, T>;
     hipLaunchKernelGGL(kern, dim3((unsigned)((p->KP + 15) / 16)), dim3(256), 0, st, (T *)dst, (const T *)p->part,
                        (const T *)p->part_curv, nch, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1, nt,
-                       (T)reg_core, (T)eta, (T)(p->N + 1), p->d.damping, acc);
+                       (T)reg_core, (T)eta, (T)(p->N + 1), p->d.damping, acc, p->d.core_kind == S3_CORE_CP ? 1 : 0);
 }
 
 template <typename T> void pad_core(s3_plan *p, hipStream_t st) {
     const int *J = p->d.rank;
+    // a hyper-diagonal core pads as a one-mode core of J values
+    const int Nc = p->d.core_kind == S3_CORE_CP ? 1 : p->N;
     hipLaunchKernelGGL(k_pad_core<T>, dim3(grid_for(p->KP, 256, 64)), dim3(256), 0, st, (const T *)p->b.G,
-                       (T *)p->Gp, p->N, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1);
+                       (T *)p->Gp, Nc, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1);
 }
 
 template <typename T> void fill(void *ptr, int64_t n, double v, hipStream_t st) {
@@ -381,6 +407,12 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
     if (d.batch < 1 || d.round_items < 1 || d.hot_rows < -1 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
     if (d.contraction != S3_CONTRACT_REUSE && d.contraction != S3_CONTRACT_NAIVE) return S3_ERR_INVALID_ARG;
+    if (d.core_kind != S3_CORE_TUCKER && d.core_kind != S3_CORE_CP) return S3_ERR_INVALID_ARG;
+    if (d.core_kind == S3_CORE_CP) {
+        for (int n = 1; n < d.order; ++n)
+            if (d.rank[n] != d.rank[0]) return S3_ERR_INVALID_ARG;
+        if (d.contraction != S3_CONTRACT_REUSE) return S3_ERR_UNSUPPORTED;
+    }
     if (!(d.eta0 > 0) || !(d.mu >= 0) || !(d.lambda_reg >= 0) || !(d.lambda_m >= 0)) return S3_ERR_INVALID_ARG;
     int Jmax = 0;
     for (int n = 0; n < d.order; ++n) {
@@ -398,13 +430,19 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     p->N = d.order;
     p->M = d.n_mat;
     p->JP = JP;
-    for (int n = 0; n < p->N; ++n) { p->K *= d.rank[n]; p->KP *= JP; }
+    if (d.core_kind == S3_CORE_CP) {
+        p->K = d.rank[0];
+        p->KP = JP;
+    } else {
+        for (int n = 0; n < p->N; ++n) { p->K *= d.rank[n]; p->KP *= JP; }
+    }
     p->exact = true;
     for (int n = 0; n < p->N; ++n) p->exact = p->exact && d.rank[n] == JP;
     p->tsize = (d.dtype == S3_F64) ? 8 : 4;
     const bool naive = d.contraction == S3_CONTRACT_NAIVE;
-    const bool ok = (d.dtype == S3_F64) ? pick_set<double>(p->N, JP, &p->ks, naive)
-                                        : pick_set<float>(p->N, JP, &p->ks, naive);
+    const bool cp = d.core_kind == S3_CORE_CP;
+    const bool ok = (d.dtype == S3_F64) ? pick_set<double>(p->N, JP, &p->ks, naive, cp)
+                                        : pick_set<float>(p->N, JP, &p->ks, naive, cp);
     if (!ok) {
         delete p;
         return S3_ERR_UNSUPPORTED;
@@ -1039,6 +1077,8 @@ extern "C" {
 s3_status s3_orthogonalize(s3_plan *p, void *stream) {
     if (!p) return S3_ERR_INVALID_ARG;
     if (!p->bound) return fail(p, S3_ERR_STATE, "s3_orthogonalize before s3_bind");
+    if (p->d.core_kind == S3_CORE_CP)
+        return fail(p, S3_ERR_UNSUPPORTED, "orthogonalisation makes a hyper-diagonal core dense");
     for (int n = 0; n < p->N; ++n)
         if (p->d.rank[n] > kQrJ || p->d.rank[n] > p->d.dims[n])
             return fail(p, S3_ERR_UNSUPPORTED, "orthogonalisation needs J_n <= min(16, I_n)");

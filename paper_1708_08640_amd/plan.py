@@ -33,7 +33,8 @@ class S3Plan:
     def __init__(self, dims: Sequence[int], ranks: Sequence[int], matrices: Sequence[Tuple[int, int]] = (),
                  dtype: str = "f32", eta0: float = 0.01, mu: float = 0.1, lambda_reg: float = 0.01,
                  lambda_m: float = 10.0, batch: int = 65536, round_items: int = 65536, damping: bool = False,
-                 seed: int = 0, device: str = "cuda", hot_rows: int = 0, contraction: str = "reuse"):
+                 seed: int = 0, device: str = "cuda", hot_rows: int = 0, contraction: str = "reuse",
+                 core: str = "tucker"):
         self.lib = load()
         if dtype not in _DTYPES:
             raise ValueError(f"dtype must be one of {list(_DTYPES)}")
@@ -62,6 +63,10 @@ class S3Plan:
         if contraction not in ("reuse", "naive"):
             raise ValueError("contraction must be 'reuse' or 'naive'")
         d.contraction = _abi.S3_CONTRACT_NAIVE if contraction == "naive" else _abi.S3_CONTRACT_REUSE
+        if core not in ("tucker", "cp"):
+            raise ValueError("core must be 'tucker' or 'cp'")
+        d.core_kind = _abi.S3_CORE_CP if core == "cp" else _abi.S3_CORE_TUCKER
+        self.core = core
         self.desc = d
         h = C.c_void_p()
         check(self.lib.s3_plan_create(C.byref(d), C.byref(h)))
@@ -129,7 +134,7 @@ class S3Plan:
     @classmethod
     def from_problem(cls, problem, params, dtype: str = "f32", batch: int = 65536, order=None,
                      damping: bool = False, round_items: int = 65536, seed: int = 0, device: str = "cuda",
-                     hot_rows: int = 0, contraction: str = "reuse", **hyper) -> "S3Plan":
+                     hot_rows: int = 0, contraction: str = "reuse", core: str = "tucker", **hyper) -> "S3Plan":
         """Plan for a generated problem (see ``synth``) with initial (U, G, V)."""
         cfg = problem.cfg
         U, G, V = params
@@ -137,7 +142,7 @@ class S3Plan:
         kw.update(hyper)
         p = cls(cfg.dims, cfg.ranks, [(s.mode, s.cols) for s in cfg.matrices], dtype=dtype, batch=batch,
                 round_items=round_items, damping=damping, seed=seed, device=device, hot_rows=hot_rows,
-                contraction=contraction, **kw)
+                contraction=contraction, core=core, **kw)
         mats = [(problem.mat_row[m], problem.mat_col[m], problem.mat_val[m]) for m in range(len(problem.mat_val))]
         p.bind(problem.train_idx, problem.train_val, problem.test_idx, problem.test_val, mats, U, G, V, order)
         return p

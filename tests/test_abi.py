@@ -63,6 +63,9 @@ def _desc(_abi, **kw):
     (dict(mat_mode=(3, 0, 0, 0)), -1),
     (dict(contraction=2), -1),
     (dict(contraction=1, rank=(8, 8, 8)), -3),  # no naive kernels for J = 8
+    (dict(core_kind=2), -1),
+    (dict(core_kind=1, rank=(10, 10, 8)), -1),  # CP needs equal ranks
+    (dict(core_kind=1, contraction=1), -3),
 ])
 def test_plan_create_rejects(kw, status):
     _abi, lib = _lib()
