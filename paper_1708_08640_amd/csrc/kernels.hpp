@@ -573,136 +573,206 @@ __global__ __launch_bounds__(256) void k_core_apply(T *__restrict__ G, const T *
 
 // ---------------------------------------------------------- det: rows apply
 
-// One wavefront per touched row (segment) of the batch; segments of more
-// than kLongSeg contributions (the power-law head rows) are left to
-// k_rows_apply_long.
+// Each touched row of a batch is a segment of the row-sorted contribution
+// list; its contributions (gradient row and curvature in the batch scratch)
+// are summed in a fixed order and applied once.  Segment lengths follow the
+// power law of the data, so three shapes share one launch:
+//   lane blocks   one lane per segment of <= kShortSeg contributions (most
+//                 rows), summed serially;
+//   wave blocks   one wavefront per segment of up to kLongSeg (bind-time
+//                 list): lanes stride the list, then a fixed butterfly;
+//   piece blocks  the longer segments cut into pieces of kPiece
+//                 contributions (bind-time list), one workgroup each, whose
+//                 sums k_rows_finish adds in piece order and applies (a
+//                 single head row would otherwise run on one CU).
+// All groups (factor matrices and coupled factors) of the batch go in the
+// same two launches.
+constexpr int64_t kShortSeg = 8;
 constexpr int64_t kLongSeg = 512;
+constexpr int64_t kPiece = 4096;
+constexpr int kRowsThreads = 256;
+constexpr int kRowsJ = 16;  // largest rank
 
-template <typename T, int JMAX>
-__global__ __launch_bounds__(256) void k_rows_apply(const uint64_t *__restrict__ contrib,
-                                                    const int64_t *__restrict__ seg_start,
-                                                    const int32_t *__restrict__ seg_row, int64_t s0,
-                                                    int64_t s1, const T *__restrict__ scr,
-                                                    T *__restrict__ P, int J, T eta, T kappa,
-                                                    int damp, int accumulate) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t s = s0 + wid; s < s1; s += nw) {
-        const int64_t c0 = seg_start[s], c1 = seg_start[s + 1];
-        if (c1 - c0 > kLongSeg) continue;  // uniform over the wavefront
-        T acc[JMAX];
+struct RowsGroup {
+    const uint64_t *contrib;    // sorted (gradient offset | curvature offset << 32)
+    const int64_t *seg_start;   // [nseg + 1]
+    const int32_t *seg_row;
+    const int32_t *med_ids;     // segments of (kShortSeg, kLongSeg] contributions
+    const int32_t *long_ids;    // longer segments
+    const int32_t *long_fp;     // first piece of each long segment (+ end)
+    const int64_t *pc0, *pc1;   // pieces: contribution ranges
+    void *P;                    // parameter (or gradient in the adjoint)
+    int J;
+    int64_t s0, s1, m0, m1, l0, l1, p0, p1;  // this batch's ranges
+    int64_t b_lane, b_med, b_piece;          // first block of each kind
+};
+
+template <typename T> struct RowsArgs {
+    RowsGroup g[kMaxN + kMaxM];
+    int G;
+    int64_t b_end;              // blocks of k_rows_reduce
+    int64_t n_long;             // long segments of the batch over all groups
+    const T *scr;
+    T *part;                    // piece sums [piece][kRowsJ + 1], pieces numbered across groups
+    int64_t part_base[kMaxN + kMaxM];
+    T eta, kappa;
+    int damp, accumulate;
+};
+
+template <typename T>
+S3_DEV void rows_update(T *P, int32_t row, int J, int k, T g, T L, const RowsArgs<T> &a) {
+    T *p = P + (int64_t)row * J + k;
+    if (a.accumulate) {
+        *p += g;
+    } else {
+        T scale = a.eta;
+        if (a.damp) {
+            const T d = a.kappa * a.eta * L;
+            scale = a.eta / (d > T(1) ? d : T(1));
+        }
+        *p -= scale * g;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowsThreads) void k_rows_reduce(RowsArgs<T> a) {
+    __shared__ T s_red[kRowsThreads / kWave][kRowsJ + 1];
+    const int64_t blk = blockIdx.x;
+    int gi = 0;
+    for (int h = 1; h < a.G; ++h)
+        if (blk >= a.g[h].b_lane) gi = h;
+    const RowsGroup &g = a.g[gi];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int J = g.J;
+    if (blk < g.b_med) {
+        // one lane per short segment
+        const int64_t s = g.s0 + (blk - g.b_lane) * kRowsThreads + tid;
+        if (s >= g.s1) return;
+        const int64_t c0 = g.seg_start[s], c1 = g.seg_start[s + 1];
+        if (c1 - c0 > kShortSeg) return;
+        T acc[kRowsJ];
 #pragma unroll
-        for (int k = 0; k < JMAX; ++k) acc[k] = T(0);
+        for (int k = 0; k < kRowsJ; ++k) acc[k] = T(0);
+        T L = T(0);
+        for (int64_t c = c0; c < c1; ++c) {
+            const uint64_t v = g.contrib[c];
+            const T *gr = a.scr + (int64_t)(v & 0xffffffffull);
+#pragma unroll
+            for (int k = 0; k < kRowsJ; ++k)
+                if (k < J) acc[k] += gr[k];
+            L += a.scr[(int64_t)(v >> 32)];
+        }
+        const int32_t row = g.seg_row[s];
+#pragma unroll
+        for (int k = 0; k < kRowsJ; ++k)
+            if (k < J) rows_update((T *)g.P, row, J, k, acc[k], L, a);
+        return;
+    }
+    if (blk < g.b_piece) {
+        // one wavefront per medium segment
+        const int64_t m = g.m0 + (blk - g.b_med) * (kRowsThreads / kWave) + wv;
+        if (m >= g.m1) return;  // uniform over the wavefront
+        const int64_t s = g.med_ids[m];
+        const int64_t c0 = g.seg_start[s], c1 = g.seg_start[s + 1];
+        T acc[kRowsJ];
+#pragma unroll
+        for (int k = 0; k < kRowsJ; ++k) acc[k] = T(0);
         T L = T(0);
         for (int64_t c = c0 + lane; c < c1; c += kWave) {
-            const uint64_t v = contrib[c];
-            const T *g = scr + (int64_t)(v & 0xffffffffull);
+            const uint64_t v = g.contrib[c];
+            const T *gr = a.scr + (int64_t)(v & 0xffffffffull);
 #pragma unroll
-            for (int k = 0; k < JMAX; ++k)
-                if (k < J) acc[k] += g[k];
-            L += scr[(int64_t)(v >> 32)];
+            for (int k = 0; k < kRowsJ; ++k)
+                if (k < J) acc[k] += gr[k];
+            L += a.scr[(int64_t)(v >> 32)];
         }
         T mine = T(0);
 #pragma unroll
-        for (int k = 0; k < JMAX; ++k) {
+        for (int k = 0; k < kRowsJ; ++k) {
+            if (k >= J) break;  // uniform
             const T t = wave_sum(acc[k]);
             if (lane == k) mine = t;
         }
         L = wave_sum(L);
-        if (lane < J) {
-            T *p = P + (int64_t)seg_row[s] * J + lane;
-            if (accumulate) {
-                *p += mine;
-            } else {
-                T scale = eta;
-                if (damp) {
-                    const T d = kappa * eta * L;
-                    scale = eta / (d > T(1) ? d : T(1));
-                }
-                *p -= scale * mine;
-            }
-        }
+        if (lane < J) rows_update((T *)g.P, g.seg_row[s], J, lane, mine, L, a);
+        return;
     }
-}
-
-// One 1,024-thread block per long segment (listed at bind time): thread t
-// sums contributions t, t + 1024, ... two at a time; the wavefronts are then
-// added in order, so the result is reproducible.
-constexpr int kLongThreads = 1024;
-
-template <typename T, int JMAX>
-__global__ __launch_bounds__(kLongThreads) void k_rows_apply_long(
-    const uint64_t *__restrict__ contrib, const int64_t *__restrict__ seg_start, const int32_t *__restrict__ seg_row,
-    const int32_t *__restrict__ long_ids, int64_t l0, const T *__restrict__ scr, T *__restrict__ P, int J, T eta,
-    T kappa, int damp, int accumulate) {
-    constexpr int NW = kLongThreads / kWave;
-    __shared__ T s_red[NW][JMAX + 1];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int64_t s = long_ids[l0 + blockIdx.x];
-    const int64_t c0 = seg_start[s], c1 = seg_start[s + 1];
-    T acc[JMAX + 1];
+    // one workgroup per piece of a long segment
+    const int64_t pc = g.p0 + (blk - g.b_piece);
+    const int64_t c0 = g.pc0[pc], c1 = g.pc1[pc];
+    T acc[kRowsJ + 1];
 #pragma unroll
-    for (int k = 0; k <= JMAX; ++k) acc[k] = T(0);
-    int64_t c = c0 + tid;
-    for (; c + kLongThreads < c1; c += 2 * kLongThreads) {
-        const uint64_t v0 = contrib[c], v1 = contrib[c + kLongThreads];
-        const T *g0 = scr + (int64_t)(v0 & 0xffffffffull);
-        const T *g1 = scr + (int64_t)(v1 & 0xffffffffull);
+    for (int k = 0; k <= kRowsJ; ++k) acc[k] = T(0);
+    for (int64_t c = c0 + tid; c < c1; c += kRowsThreads) {
+        const uint64_t v = g.contrib[c];
+        const T *gr = a.scr + (int64_t)(v & 0xffffffffull);
 #pragma unroll
-        for (int k = 0; k < JMAX; ++k)
-            if (k < J) acc[k] += g0[k] + g1[k];
-        acc[JMAX] += scr[(int64_t)(v0 >> 32)] + scr[(int64_t)(v1 >> 32)];
-    }
-    if (c < c1) {
-        const uint64_t v = contrib[c];
-        const T *g = scr + (int64_t)(v & 0xffffffffull);
-#pragma unroll
-        for (int k = 0; k < JMAX; ++k)
-            if (k < J) acc[k] += g[k];
-        acc[JMAX] += scr[(int64_t)(v >> 32)];
+        for (int k = 0; k < kRowsJ; ++k)
+            if (k < J) acc[k] += gr[k];
+        acc[kRowsJ] += a.scr[(int64_t)(v >> 32)];
     }
 #pragma unroll
-    for (int k = 0; k <= JMAX; ++k) {
+    for (int k = 0; k <= kRowsJ; ++k) {
         const T t = wave_sum(acc[k]);
         if (lane == 0) s_red[wv][k] = t;
     }
     __syncthreads();
-    if (tid >= J) return;
-    T mine = T(0), L = T(0);
-    for (int w = 0; w < NW; ++w) {
-        mine += s_red[w][tid];
-        L += s_red[w][JMAX];
-    }
-    T *p = P + (int64_t)seg_row[s] * J + tid;
-    if (accumulate) {
-        *p += mine;
-    } else {
-        T scale = eta;
-        if (damp) {
-            const T d = kappa * eta * L;
-            scale = eta / (d > T(1) ? d : T(1));
-        }
-        *p -= scale * mine;
+    if (tid <= kRowsJ) {
+        T t = T(0);
+        for (int w = 0; w < kRowsThreads / kWave; ++w) t += s_red[w][tid];
+        a.part[(a.part_base[gi] + pc - g.p0) * (kRowsJ + 1) + tid] = t;
     }
 }
 
-// bind time: the segments longer than kLongSeg, in order, with their batch
-__global__ void k_long_flags(const int64_t *__restrict__ seg_start, int64_t nseg, int32_t *__restrict__ flag) {
+// one wavefront per long segment (over all groups): its pieces in order
+template <typename T>
+__global__ __launch_bounds__(kRowsThreads) void k_rows_finish(RowsArgs<T> a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int64_t w = ((int64_t)blockIdx.x * kRowsThreads + threadIdx.x) / kWave;
+    if (w >= a.n_long) return;
+    int gi = 0;
+    for (; gi < a.G; ++gi) {
+        const int64_t nl = a.g[gi].l1 - a.g[gi].l0;
+        if (w < nl) break;
+        w -= nl;
+    }
+    const RowsGroup &g = a.g[gi];
+    const int64_t li = g.l0 + w;
+    const int J = g.J;
+    if (lane > J) return;
+    T t = T(0);
+    for (int64_t pc = g.long_fp[li]; pc < g.long_fp[li + 1]; ++pc)
+        t += a.part[(a.part_base[gi] + pc - g.p0) * (kRowsJ + 1) + (lane < J ? lane : kRowsJ)];
+    const T L = __shfl(t, J, kWave);
+    if (lane < J) rows_update((T *)g.P, g.seg_row[g.long_ids[li]], J, lane, t, L, a);
+}
+
+// bind time: the segments with lo < length <= hi, in order, with their batch
+__global__ void k_seg_class(const int64_t *__restrict__ seg_start, int64_t nseg, int64_t lo, int64_t hi,
+                            int32_t *__restrict__ flag) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; s < nseg; s += stride) flag[s] = (seg_start[s + 1] - seg_start[s] > kLongSeg) ? 1 : 0;
+    for (; s < nseg; s += stride) {
+        const int64_t len = seg_start[s + 1] - seg_start[s];
+        flag[s] = (len > lo && len <= hi) ? 1 : 0;
+    }
 }
 
-__global__ void k_long_write(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t nseg,
-                             const uint32_t *__restrict__ seg_batch, int32_t *__restrict__ long_ids,
-                             uint32_t *__restrict__ long_batch) {
+__global__ void k_seg_list(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t nseg,
+                           const uint32_t *__restrict__ seg_batch, const int64_t *__restrict__ seg_start,
+                           int32_t *__restrict__ ids, uint32_t *__restrict__ batch, int64_t *__restrict__ c0,
+                           int64_t *__restrict__ c1) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; s < nseg; s += stride)
         if (flag[s]) {
-            long_ids[pos[s] - 1] = (int32_t)s;
-            long_batch[pos[s] - 1] = seg_batch[s];
+            const int64_t i = pos[s] - 1;
+            ids[i] = (int32_t)s;
+            batch[i] = seg_batch[s];
+            if (c0) {
+                c0[i] = seg_start[s];
+                c1[i] = seg_start[s + 1];
+            }
         }
 }
 

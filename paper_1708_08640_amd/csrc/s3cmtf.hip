@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -28,11 +29,14 @@ struct Group {
     uint64_t *contrib = nullptr;  // sorted (goff | coff << 32)
     int64_t *seg_start = nullptr; // [nseg + 1]
     int32_t *seg_row = nullptr;   // [nseg]
-    int32_t *long_ids = nullptr;  // segments longer than kLongSeg, in order
+    int32_t *med_ids = nullptr;   // segments of (kShortSeg, kLongSeg] contributions
+    int32_t *long_ids = nullptr;  // longer segments, in order
+    int32_t *long_fp = nullptr;   // first piece of each long segment (+ end)
+    int64_t *pc0 = nullptr, *pc1 = nullptr;  // pieces of the long segments
     int64_t n_valid = 0;
     int64_t nseg = 0;
-    std::vector<int64_t> h_boff;  // per-batch segment ranges
-    std::vector<int64_t> h_loff;  // per-batch ranges of long_ids
+    std::vector<int64_t> h_boff;  // per-batch ranges: segments, medium, long, pieces
+    std::vector<int64_t> h_moff, h_loff, h_poff;
     int J = 0;
     int64_t rows = 0;
 };
@@ -92,6 +96,7 @@ struct s3_plan {
     int64_t m_base[S3_MAX_MATRICES] = {}, m_stride[S3_MAX_MATRICES] = {};
     void *part = nullptr, *part_curv = nullptr;
     int64_t max_chunks = 0;
+    void *rows_part = nullptr;  // piece sums of the long segments of one batch
     bool det_ready = false;
     // lock-free structures
     LockFreeState lf;
@@ -284,21 +289,57 @@ hipError_t prof_mark(s3_plan *p, size_t k, hipStream_t st) {
 double eta_of(const s3_desc &d, int epoch) { return d.eta0 / (1.0 + d.mu * (double)epoch); }
 
 // launch helper for the row-apply kernel (J <= 16)
+// the batch's row updates of every group: one reduce launch, and one finish
+// launch when some row has more than kLongSeg contributions
 template <typename T>
-void rows_apply(const Group &g, int64_t b, const void *scr, void *P, double eta, double kappa, int damp, int acc,
+void rows_apply(s3_plan *p, int64_t b, void *const *P, double eta, double kappa, int damp, int acc,
                 hipStream_t st) {
-    const int64_t s0 = g.h_boff[b], s1 = g.h_boff[b + 1];
-    const int64_t nseg = s1 - s0;
-    if (nseg <= 0) return;
-    const int tpb = 256;
-    hipLaunchKernelGGL((k_rows_apply<T, 16>), dim3(grid_for(nseg * kWave, tpb, 1ll << 20)), dim3(tpb), 0, st,
-                       g.contrib, g.seg_start, g.seg_row, s0, s1, (const T *)scr, (T *)P, g.J, (T)eta,
-                       (T)kappa, damp, acc);
-    const int64_t l0 = g.h_loff[b], nl = g.h_loff[b + 1] - l0;
-    if (nl > 0)
-        hipLaunchKernelGGL((k_rows_apply_long<T, 16>), dim3((unsigned)nl), dim3(kLongThreads), 0, st, g.contrib,
-                           g.seg_start, g.seg_row, g.long_ids, l0, (const T *)scr, (T *)P, g.J, (T)eta, (T)kappa,
-                           damp, acc);
+    RowsArgs<T> a{};
+    a.G = p->N + p->M;
+    a.scr = (const T *)p->scr;
+    a.part = (T *)p->rows_part;
+    a.eta = (T)eta;
+    a.kappa = (T)kappa;
+    a.damp = damp;
+    a.accumulate = acc;
+    int64_t blk = 0, pieces = 0;
+    for (int gi = 0; gi < a.G; ++gi) {
+        const Group &G = p->grp[gi];
+        RowsGroup &r = a.g[gi];
+        r.contrib = G.contrib;
+        r.seg_start = G.seg_start;
+        r.seg_row = G.seg_row;
+        r.med_ids = G.med_ids;
+        r.long_ids = G.long_ids;
+        r.long_fp = G.long_fp;
+        r.pc0 = G.pc0;
+        r.pc1 = G.pc1;
+        r.P = P[gi];
+        r.J = G.J;
+        const bool any = G.nseg > 0;
+        r.s0 = any ? G.h_boff[b] : 0;
+        r.s1 = any ? G.h_boff[b + 1] : 0;
+        r.m0 = any ? G.h_moff[b] : 0;
+        r.m1 = any ? G.h_moff[b + 1] : 0;
+        r.l0 = any ? G.h_loff[b] : 0;
+        r.l1 = any ? G.h_loff[b + 1] : 0;
+        r.p0 = any ? G.h_poff[b] : 0;
+        r.p1 = any ? G.h_poff[b + 1] : 0;
+        r.b_lane = blk;
+        blk += (r.s1 - r.s0 + kRowsThreads - 1) / kRowsThreads;
+        r.b_med = blk;
+        blk += (r.m1 - r.m0 + kRowsThreads / kWave - 1) / (kRowsThreads / kWave);
+        r.b_piece = blk;
+        blk += r.p1 - r.p0;
+        a.part_base[gi] = pieces;
+        pieces += r.p1 - r.p0;
+        a.n_long += r.l1 - r.l0;
+    }
+    a.b_end = blk;
+    if (blk > 0) hipLaunchKernelGGL(k_rows_reduce<T>, dim3((unsigned)blk), dim3(kRowsThreads), 0, st, a);
+    if (a.n_long > 0)
+        hipLaunchKernelGGL(k_rows_finish<T>, dim3((unsigned)((a.n_long * kWave + kRowsThreads - 1) / kRowsThreads)),
+                           dim3(kRowsThreads), 0, st, a);
 }
 
 template <typename T>
@@ -360,11 +401,10 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
                            adj ? (const T *)gy[m] : (const T *)nullptr);
     }
     if (nt > 0) p->ks.core_partial(p, p->sorted_ids + t0, nt, st);
-    for (int g = 0; g < p->N + M; ++g) {
-        const Group &G = p->grp[g];
-        void *P = (g < p->N) ? (adj ? dU[g] : p->b.U[g]) : (adj ? dV[g - p->N] : p->b.V[g - p->N]);
-        rows_apply<T>(G, b, p->scr, P, eta, (double)(p->N + 1), p->d.damping, adj ? 1 : 0, st);
-    }
+    void *P[S3_MAX_ORDER + S3_MAX_MATRICES];
+    for (int g = 0; g < p->N + M; ++g)
+        P[g] = (g < p->N) ? (adj ? dU[g] : p->b.U[g]) : (adj ? dV[g - p->N] : p->b.V[g - p->N]);
+    rows_apply<T>(p, b, P, eta, (double)(p->N + 1), p->d.damping, adj ? 1 : 0, st);
     if (nt > 0) core_apply<T>(p, nt, eta, adj ? 1 : 0, adj ? dG : p->b.G, st);
 }
 
@@ -551,7 +591,11 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
             p->grp[g].contrib = c.take<uint64_t>((size_t)std::max<int64_t>(nv, 1));
             p->grp[g].seg_start = c.take<int64_t>((size_t)nv + 1);
             p->grp[g].seg_row = c.take<int32_t>((size_t)std::max<int64_t>(nv, 1));
+            p->grp[g].med_ids = c.take<int32_t>((size_t)(nv / kShortSeg + 1));
             p->grp[g].long_ids = c.take<int32_t>((size_t)(nv / kLongSeg + 1));
+            p->grp[g].long_fp = c.take<int32_t>((size_t)(nv / kLongSeg + 2));
+            p->grp[g].pc0 = c.take<int64_t>((size_t)(nv / kPiece + nv / kLongSeg + 2));
+            p->grp[g].pc1 = c.take<int64_t>((size_t)(nv / kPiece + nv / kLongSeg + 2));
         }
         // per-batch scratch
         const int64_t RJ = (int64_t)N * p->JP;  // gradient rows at a fixed JP stride
@@ -569,6 +613,9 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
         p->max_chunks = (max_nt + kChunk - 1) / kChunk;
         p->part = c.take<T>((size_t)(p->max_chunks * p->KP));
         p->part_curv = c.take<T>((size_t)p->max_chunks);
+        // piece sums of one batch: every group's contributions in pieces,
+        // plus one partial piece per long segment
+        p->rows_part = c.take<T>((size_t)(N + M) * (B / kPiece + B / kLongSeg + 2) * (kRowsJ + 1));
         // bind-time temporaries (same carve as build_det, from an aligned start)
         c.off = (c.off + 255) & ~(size_t)255;
         const size_t t0 = c.off;
@@ -651,7 +698,9 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
         HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(temp, tb, gk_in, gk_out, gv_in, gv_out, (int)n, 0, 64, st));
         const int64_t nv = G.n_valid;
         G.h_boff.assign((size_t)nb + 1, 0);
+        G.h_moff.assign((size_t)nb + 1, 0);
         G.h_loff.assign((size_t)nb + 1, 0);
+        G.h_poff.assign((size_t)nb + 1, 0);
         if (nv == 0) { G.nseg = 0; continue; }
         HIPCHK(p, hipMemcpyAsync(G.contrib, gv_out, sizeof(uint64_t) * nv, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, st, gk_out, nv, flags);
@@ -666,21 +715,54 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
                            G.nseg, nb, boff);
         HIPCHK(p, hipMemcpyAsync(G.h_boff.data(), boff, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st));
         HIPCHK(p, hipStreamSynchronize(st));
-        // the long segments (one block each at apply time), per batch
+        // medium and long segments per batch; the long ones cut into pieces
+        G.h_moff.assign((size_t)nb + 1, 0);
+        G.h_poff.assign((size_t)nb + 1, 0);
         if (G.nseg == 0) continue;
-        hipLaunchKernelGGL(k_long_flags, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, G.seg_start, G.nseg,
-                           flags);
-        HIPCHK(p, hipcub::DeviceScan::InclusiveSum(temp, tb, flags, segid, (int)G.nseg, st));
-        int32_t nlong = 0;
-        HIPCHK(p, hipMemcpyAsync(&nlong, segid + G.nseg - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(p, hipStreamSynchronize(st));
-        if (nlong == 0) continue;
         uint32_t *lbatch = (uint32_t *)gk_in;  // free once this group's keys are sorted
-        hipLaunchKernelGGL(k_long_write, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, flags, segid,
-                           G.nseg, segb, G.long_ids, lbatch);
-        hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(nlong + 1, 256, 16384)), dim3(256), 0, st, lbatch,
-                           (int64_t)nlong, nb, boff);
-        HIPCHK(p, hipMemcpyAsync(G.h_loff.data(), boff, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st));
+        int64_t *lc0 = (int64_t *)gv_in;       // likewise
+        auto list = [&](int64_t lo, int64_t hi, int32_t *ids, std::vector<int64_t> &h_off, bool bounds,
+                        int64_t *count) -> s3_status {
+            hipLaunchKernelGGL(k_seg_class, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, G.seg_start,
+                               G.nseg, lo, hi, flags);
+            HIPCHK(p, hipcub::DeviceScan::InclusiveSum(temp, tb, flags, segid, (int)G.nseg, st));
+            int32_t n32 = 0;
+            HIPCHK(p, hipMemcpyAsync(&n32, segid + G.nseg - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipStreamSynchronize(st));
+            *count = n32;
+            if (n32 == 0) return S3_OK;
+            hipLaunchKernelGGL(k_seg_list, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, flags, segid,
+                               G.nseg, segb, G.seg_start, ids, lbatch, bounds ? lc0 : (int64_t *)nullptr,
+                               bounds ? lc0 + n32 : (int64_t *)nullptr);
+            hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(n32 + 1, 256, 16384)), dim3(256), 0, st, lbatch,
+                               (int64_t)n32, nb, boff);
+            HIPCHK(p, hipMemcpyAsync(h_off.data(), boff, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipStreamSynchronize(st));
+            return S3_OK;
+        };
+        int64_t nmed = 0, nlong = 0;
+        s3_status ls = list(kShortSeg, kLongSeg, G.med_ids, G.h_moff, false, &nmed);
+        if (ls != S3_OK) return ls;
+        ls = list(kLongSeg, INT64_MAX, G.long_ids, G.h_loff, true, &nlong);
+        if (ls != S3_OK) return ls;
+        if (nlong == 0) continue;
+        std::vector<int64_t> c01((size_t)(2 * nlong));
+        HIPCHK(p, hipMemcpyAsync(c01.data(), lc0, sizeof(int64_t) * 2 * nlong, hipMemcpyDeviceToHost, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+        std::vector<int32_t> fp((size_t)nlong + 1);
+        std::vector<int64_t> q0, q1;
+        for (int64_t i = 0; i < nlong; ++i) {
+            fp[(size_t)i] = (int32_t)q0.size();
+            for (int64_t c = c01[(size_t)i]; c < c01[(size_t)(nlong + i)]; c += kPiece) {
+                q0.push_back(c);
+                q1.push_back(std::min<int64_t>(c + kPiece, c01[(size_t)(nlong + i)]));
+            }
+        }
+        fp[(size_t)nlong] = (int32_t)q0.size();
+        for (int64_t bb = 0; bb <= nb; ++bb) G.h_poff[(size_t)bb] = fp[(size_t)G.h_loff[(size_t)bb]];
+        HIPCHK(p, hipMemcpyAsync(G.long_fp, fp.data(), sizeof(int32_t) * fp.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(p, hipMemcpyAsync(G.pc0, q0.data(), sizeof(int64_t) * q0.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(p, hipMemcpyAsync(G.pc1, q1.data(), sizeof(int64_t) * q1.size(), hipMemcpyHostToDevice, st));
         HIPCHK(p, hipStreamSynchronize(st));
     }
     p->det_ready = true;
