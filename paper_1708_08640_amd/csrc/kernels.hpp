@@ -20,6 +20,10 @@
 // All reductions have a fixed order, so a det-mode run is bitwise
 // reproducible.
 #pragma once
+#include <hipcub/block/block_radix_sort.hpp>
+
+#include <cstdint>
+
 #include "common.hpp"
 #include "contract.hpp"
 
@@ -53,10 +57,38 @@ __global__ void k_check_range(const int32_t *__restrict__ idx, int64_t n, int64_
     if (bad) atomicOr(flag, 1);
 }
 
-__global__ void k_hist(const int32_t *__restrict__ idx, int64_t n, int32_t *__restrict__ cnt) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) atomicAdd(&cnt[idx[i]], 1);
+// Row counts.  Power-law indices make plain per-entry atomics serialise on
+// the head rows, so each workgroup sorts a chunk of kHistItems x 256 indices
+// in LDS and adds one count per run of equal indices in a lane's items.
+constexpr int kHistItems = 16;
+
+__global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ idx, int64_t n,
+                                              int32_t *__restrict__ cnt) {
+    using Sort = hipcub::BlockRadixSort<int32_t, 256, kHistItems>;
+    __shared__ typename Sort::TempStorage tmp;
+    constexpr int64_t kChunkItems = 256 * kHistItems;
+    for (int64_t base = (int64_t)blockIdx.x * kChunkItems; base < n; base += (int64_t)gridDim.x * kChunkItems) {
+        int32_t k[kHistItems];
+#pragma unroll
+        for (int i = 0; i < kHistItems; ++i) {
+            const int64_t e = base + (int64_t)i * 256 + threadIdx.x;  // coalesced
+            k[i] = (e < n) ? idx[e] : INT32_MAX;
+        }
+        __syncthreads();  // the previous chunk's sort storage is free
+        Sort(tmp).Sort(k);  // lane t now holds ranks 16 t .. 16 t + 15
+        int32_t cur = k[0], run = 1;
+#pragma unroll
+        for (int i = 1; i < kHistItems; ++i) {
+            if (k[i] == cur) {
+                ++run;
+            } else {
+                if (cur != INT32_MAX) atomicAdd(&cnt[cur], run);
+                cur = k[i];
+                run = 1;
+            }
+        }
+        if (cur != INT32_MAX) atomicAdd(&cnt[cur], run);
+    }
 }
 
 // key = batch * (M + 1) + type (0 tensor, m + 1 matrix m); value = item id
