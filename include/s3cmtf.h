@@ -114,7 +114,9 @@ typedef struct {
     int32_t rank[S3_MAX_ORDER];          /* J_n                              */
     int32_t mat_mode[S3_MAX_MATRICES];   /* c_m, coupled tensor mode         */
     int64_t mat_cols[S3_MAX_MATRICES];   /* K_m                              */
-    int32_t dtype;                       /* S3_F64, S3_F32 or S3_BF16        */
+    int32_t dtype;                       /* S3_F64 or S3_F32 (S3_BF16 is
+                                            reserved and gives
+                                            S3_ERR_UNSUPPORTED)               */
     int32_t damping;                     /* S3_DAMP_*                        */
     double eta0, mu, lambda_reg, lambda_m;
     int64_t batch;                       /* det mode: items per batch (>= 1) */
@@ -138,8 +140,8 @@ typedef struct {
 } s3_desc;
 
 /* Device buffers handed to s3_bind.  Values and parameters are `double` for
- * S3_F64 and `float` otherwise (for S3_BF16 the float arrays are the master
- * copies and *_bf16 hold the bf16 working copies the MFMA kernels read).   */
+ * S3_F64 and `float` for S3_F32.  The *_bf16 fields are reserved for a bf16
+ * working-copy mode that this library does not provide; leave them null.   */
 typedef struct {
     const int32_t *x_idx;  const void *x_val;  int64_t x_nnz;   /* training */
     const int32_t *t_idx;  const void *t_val;  int64_t t_nnz;   /* held-out */
@@ -245,8 +247,9 @@ s3_status s3_export(s3_plan *plan, int32_t which, int32_t index, double *host_ds
  * partly transformed.  Synchronous.                                        */
 s3_status s3_orthogonalize(s3_plan *plan, void *stream);
 
-/* BF16 plans: round the float masters to the bf16 working copies
- * (round-to-nearest-even).  Call after filling the masters.  Asynchronous. */
+/* Reserved for bf16 working copies of float masters.  This library has no
+ * bf16 mode (S3_BF16 plans are rejected), so it always returns
+ * S3_ERR_UNSUPPORTED (S3_ERR_INVALID_ARG for a null plan).                 */
 s3_status s3_sync_bf16(s3_plan *plan, void *stream);
 
 /* Turn per-launch timing of the dominant kernel (the tensor-entry kernel of

@@ -8,13 +8,14 @@
 //                     -e to a per-batch scratch row
 //   k_det_matrix      one lane per coupled-matrix entry: u.v, e, both row
 //                     gradients of Eq (8)
-//   k_core_partial    core gradient sum_t (-e_t) u^(1)_t o ... o u^(N)_t
-//                     over a fixed chunk of entries: each thread owns one
-//                     index of modes 2..N and all J_1 accumulators, entries
-//                     are staged through LDS
-//   k_rows_apply      one wavefront per touched row: sums that row's
-//                     contributions in a fixed order (lanes stride the list,
-//                     then a fixed butterfly), applies -eta * sum
+//   k_core_partial_mfma / k_core_partial / k_core_partial_cp
+//                     core gradient sum_t (-e_t) u^(1)_t o ... o u^(N)_t
+//                     over a fixed chunk of 256 entries (FP32 matrix cores;
+//                     FP64 VALU; hyper-diagonal core)
+//   k_rows_reduce     every touched row's contributions summed in a fixed
+//                     order and applied (-eta * sum, damped): a lane, a
+//                     wavefront or pieces of a workgroup each, by row length
+//   k_rows_finish     the pieces of the longest rows, in order
 //   k_core_apply      sums the chunk partials in order, adds the
 //                     regulariser, applies
 // All reductions have a fixed order, so a det-mode run is bitwise

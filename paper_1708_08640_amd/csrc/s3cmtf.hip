@@ -443,7 +443,9 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     const s3_desc &d = *desc;
     if (d.order < 3 || d.order > S3_MAX_ORDER) return S3_ERR_UNSUPPORTED;
     if (d.n_mat < 0 || d.n_mat > S3_MAX_MATRICES) return S3_ERR_INVALID_ARG;
-    if (d.dtype != S3_F64 && d.dtype != S3_F32 && d.dtype != S3_BF16) return S3_ERR_UNSUPPORTED;
+    // FP64 and FP32 only: bf16 copies would add traffic to every row update
+    // (the FP32 master must still be read), and the contraction is on the VALU
+    if (d.dtype != S3_F64 && d.dtype != S3_F32) return S3_ERR_UNSUPPORTED;
     if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
     if (d.batch < 1 || d.round_items < 1 || d.hot_rows < -1 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
     if (d.contraction != S3_CONTRACT_REUSE && d.contraction != S3_CONTRACT_NAIVE) return S3_ERR_INVALID_ARG;

@@ -56,6 +56,7 @@ def _desc(_abi, **kw):
     (dict(order=2), -3),
     (dict(order=5), -3),
     (dict(dtype=7), -3),
+    (dict(dtype=2), -3),  # bf16 is reserved, not provided
     (dict(rank=(10, 10, 40)), -3),
     (dict(batch=0), -1),
     (dict(eta0=-1.0), -1),
