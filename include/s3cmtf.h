@@ -18,11 +18,15 @@
  *                     values, gradients are summed per parameter in a fixed
  *                     order and applied once (batch = 1 is Algorithm 1 with
  *                     one worker).  Bitwise reproducible run to run.
- *   S3_LOCKFREE       lock-free parallel SGD (Section 3.3): many entries in
- *                     flight at once, factor rows updated without locks by
- *                     atomic read-modify-writes, so the write order differs
- *                     from run to run.  See s3_desc.damping for how updates
- *                     that overlap on one row are combined.
+ *   S3_LOCKFREE       lock-free parallel SGD (Section 3.3): the items of a
+ *                     round (s3_desc.round_items) are in flight at once; a
+ *                     factor row is updated without locks by a plain
+ *                     read-modify-write as soon as its entry is processed,
+ *                     so the write order differs from run to run.  The
+ *                     most frequent rows of each mode and coupled factor
+ *                     (s3_desc.hot_rows) and the core are instead summed
+ *                     over the round and moved once, damped (see
+ *                     s3_desc.damping).
  *
  * Layouts (device memory unless stated; all indices 0-based, int32):
  *   tensor entries   idx[n * nnz + e] = mode-n index of entry e (SoA)
@@ -89,7 +93,8 @@ enum { S3_DAMP_NONE = 0, S3_DAMP_CURVATURE = 1 };       /* s3_desc.damping */
  * -eta * sum.  S3_DAMP_CURVATURE divides that step by max(1, (N+1) eta L),
  * where L sums, over the same contributions, the curvature of the entry's
  * squared error along the block (|w_n|^2 for a tensor row, prod_n |u^(n)|^2
- * for the core, lambda_m |v|^2 and lambda_m |u|^2 for a matrix entry) plus
+ * for the core -- sum_r prod_n u^(n)_r^2 for a hyper-diagonal core --,
+ * lambda_m |v|^2 and lambda_m |u|^2 for a matrix entry) plus
  * the regularisation weight.  A block touched once with (N+1) eta L <= 1
  * moves exactly as one SGD step; a block that many concurrent entries touch
  * can no longer overshoot (N+1 bounds the joint step of the N rows and the
@@ -205,7 +210,8 @@ s3_status s3_det_batches(s3_plan *plan, int64_t first, int64_t count, double eta
 s3_status s3_loss(s3_plan *plan, double *out, void *stream);
 
 /* Held-out RMSE, sqrt(mean over test entries of (x - x~)^2) (Section 4.1,
- * "Measure").  Synchronous; S3_ERR_NONFINITE if not finite.              */
+ * "Measure"); 0 when the plan was bound without held-out entries.
+ * Synchronous; S3_ERR_NONFINITE if not finite.                           */
 s3_status s3_rmse(s3_plan *plan, double *out, void *stream);
 
 /* Forward of the prediction map: x~ for nnz entries idx (device, SoA) into
