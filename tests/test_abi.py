@@ -104,3 +104,32 @@ def test_status_strings():
     _abi, lib = _lib()
     for st in range(-7, 1):
         assert lib.s3_status_string(st)
+
+
+def test_bind_rejects_small_workspace():
+    # the size check comes before any device access, so placeholder device
+    # addresses never get dereferenced
+    _abi, lib = _lib()
+    d = _desc(_abi)
+    h = C.c_void_p()
+    assert lib.s3_plan_create(C.byref(d), C.byref(h)) == 0
+    try:
+        b = _abi.S3Buffers()
+        fake = 0x10000
+        b.x_idx, b.x_val, b.x_nnz = fake, fake, 1000
+        for n in range(3):
+            b.U[n] = fake
+        b.G, b.V[0] = fake, fake
+        b.y_row[0], b.y_col[0], b.y_val[0], b.y_nnz[0] = fake, fake, fake, 100
+        need = C.c_size_t()
+        y = (C.c_int64 * 1)(100)
+        assert lib.s3_workspace_size(h, 1000, 0, y, C.byref(need)) == 0
+        # (without an item order the bind needs less than this upper bound,
+        # so probe well below it)
+        assert lib.s3_bind(h, C.byref(b), C.c_void_p(fake), 4096, None) == -6
+        assert lib.s3_bind(h, C.byref(b), None, need.value, None) == -6
+        buf = C.create_string_buffer(256)
+        lib.s3_last_error(h, buf, 256)
+        assert b"workspace" in buf.value
+    finally:
+        lib.s3_plan_destroy(h)

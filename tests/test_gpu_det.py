@@ -99,3 +99,21 @@ def test_loss_rmse_predict_match_oracle(name, dtype):
     for m in range(len(p.mat_val)):
         got = plan.predict_matrix(m, p.mat_row[m], p.mat_col[m]).cpu().numpy()
         assert rel(got, oracle.matrix_predict(ref, m, p.mat_row[m], p.mat_col[m])) <= tol
+
+
+def test_resume_from_exported_parameters_is_exact():
+    """Checkpoint and resume: the step size depends only on the epoch index
+    and det mode's order is fixed, so exporting the parameters after epoch 0
+    and binding them to a fresh plan for epoch 1 reproduces the uninterrupted
+    run bitwise."""
+    from paper_1708_08640_amd import S3Plan
+    cfg, p, plan, ref, order = setup("cfg1", "f64", 500, True)
+    plan.epoch(0, "det")
+    mid = plan.params_numpy()
+    plan.epoch(1, "det")
+    straight = plan.params_numpy()
+    resumed = S3Plan.from_problem(p, mid, dtype="f64", batch=500, order=order, damping=True)
+    resumed.epoch(1, "det")
+    for a, b in zip(straight[0] + [straight[1]] + straight[2],
+                    resumed.params_numpy()[0] + [resumed.params_numpy()[1]] + resumed.params_numpy()[2]):
+        assert np.array_equal(a, b)
