@@ -615,14 +615,15 @@ __global__ __launch_bounds__(256) void k_core_apply(T *__restrict__ G, const T *
 //   wave blocks   one wavefront per segment of up to kLongSeg (bind-time
 //                 list): lanes stride the list, then a fixed butterfly;
 //   piece blocks  the longer segments cut into pieces of kPiece
-//                 contributions (bind-time list), one workgroup each, whose
+//                 contributions (bind-time list), one workgroup each (four
+//                 contributions per lane, two loads in flight), whose
 //                 sums k_rows_finish adds in piece order and applies (a
 //                 single head row would otherwise run on one CU).
 // All groups (factor matrices and coupled factors) of the batch go in the
 // same two launches.
 constexpr int64_t kShortSeg = 8;
 constexpr int64_t kLongSeg = 512;
-constexpr int64_t kPiece = 4096;
+constexpr int64_t kPiece = 1024;
 constexpr int kRowsThreads = 256;
 constexpr int kRowsJ = 16;  // largest rank
 
@@ -687,13 +688,18 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_reduce(RowsArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < kRowsJ; ++k) acc[k] = T(0);
         T L = T(0);
-        for (int64_t c = c0; c < c1; ++c) {
-            const uint64_t v = g.contrib[c];
-            const T *gr = a.scr + (int64_t)(v & 0xffffffffull);
+        // every contribution index first, then the rows: two round trips
+        uint64_t v[kShortSeg];
+#pragma unroll
+        for (int i = 0; i < kShortSeg; ++i) v[i] = (c0 + i < c1) ? g.contrib[c0 + i] : 0;
+#pragma unroll
+        for (int i = 0; i < kShortSeg; ++i) {
+            if (c0 + i >= c1) break;
+            const T *gr = a.scr + (int64_t)(v[i] & 0xffffffffull);
 #pragma unroll
             for (int k = 0; k < kRowsJ; ++k)
                 if (k < J) acc[k] += gr[k];
-            L += a.scr[(int64_t)(v >> 32)];
+            L += a.scr[(int64_t)(v[i] >> 32)];
         }
         const int32_t row = g.seg_row[s];
 #pragma unroll
@@ -711,7 +717,17 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_reduce(RowsArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < kRowsJ; ++k) acc[k] = T(0);
         T L = T(0);
-        for (int64_t c = c0 + lane; c < c1; c += kWave) {
+        int64_t c = c0 + lane;
+        for (; c + kWave < c1; c += 2 * kWave) {
+            const uint64_t v0 = g.contrib[c], v1 = g.contrib[c + kWave];
+            const T *g0 = a.scr + (int64_t)(v0 & 0xffffffffull);
+            const T *g1 = a.scr + (int64_t)(v1 & 0xffffffffull);
+#pragma unroll
+            for (int k = 0; k < kRowsJ; ++k)
+                if (k < J) acc[k] += g0[k] + g1[k];
+            L += a.scr[(int64_t)(v0 >> 32)] + a.scr[(int64_t)(v1 >> 32)];
+        }
+        if (c < c1) {
             const uint64_t v = g.contrib[c];
             const T *gr = a.scr + (int64_t)(v & 0xffffffffull);
 #pragma unroll
@@ -736,7 +752,17 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_reduce(RowsArgs<T> a) {
     T acc[kRowsJ + 1];
 #pragma unroll
     for (int k = 0; k <= kRowsJ; ++k) acc[k] = T(0);
-    for (int64_t c = c0 + tid; c < c1; c += kRowsThreads) {
+    int64_t c = c0 + tid;
+    for (; c + kRowsThreads < c1; c += 2 * kRowsThreads) {
+        const uint64_t v0 = g.contrib[c], v1 = g.contrib[c + kRowsThreads];
+        const T *g0 = a.scr + (int64_t)(v0 & 0xffffffffull);
+        const T *g1 = a.scr + (int64_t)(v1 & 0xffffffffull);
+#pragma unroll
+        for (int k = 0; k < kRowsJ; ++k)
+            if (k < J) acc[k] += g0[k] + g1[k];
+        acc[kRowsJ] += a.scr[(int64_t)(v0 >> 32)] + a.scr[(int64_t)(v1 >> 32)];
+    }
+    if (c < c1) {
         const uint64_t v = g.contrib[c];
         const T *gr = a.scr + (int64_t)(v & 0xffffffffull);
 #pragma unroll
