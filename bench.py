@@ -228,11 +228,12 @@ def main():
             target = 1.01 * g["rmse"][E - 1]
 
     mat_flops = sum(matrix_entry_flops(cfg.ranks[s.mode]) * len(p.mat_val[m]) for m, s in enumerate(cfg.matrices))
-    # the lock-free tensor launch also runs the round's matrix tiles
-    flops = (tensor_entry_flops(cfg.ranks) * p.n_train + (mat_flops if args.mode == "lockfree" else 0)) * args.steps
+    # the timed launch (lock-free: k_lf_tensor; det: k_det_entries) also runs
+    # the matrix entries
+    flops = (tensor_entry_flops(cfg.ranks) * p.n_train + mat_flops) * args.steps
     achieved = flops / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else None
     roofline = {
-        "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_tensor",
+        "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_entries",
         "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
         "traffic": profiled_traffic("k_lf_tensor") if args.mode == "lockfree" and cfg.name == "cfg2_zipf_10m" else None,
@@ -248,8 +249,7 @@ def main():
         J = cfg.ranks[0]
         t_bytes = 4 * cfg.order + 4 + 2 * 4 * J * cfg.order
         m_bytes = 12 + 2 * 2 * 4 * J
-        nbytes = (t_bytes * p.n_train + (m_bytes * (n_updates - p.n_train) if args.mode == "lockfree" else 0)) * \
-            args.steps
+        nbytes = (t_bytes * p.n_train + m_bytes * (n_updates - p.n_train)) * args.steps
         gbs = nbytes / (kernel_ms / 1e3) / 1e9 if kernel_ms > 0 else None
         roofline.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": (gbs / PEAK_HBM_GBS) if gbs else None, "traffic": None,

@@ -1,23 +1,22 @@
 // gfx950 kernels for sparse coupled Tucker SGD.
 //
 // Hot path of one deterministic mini-batch step (item order cut into
-// batches; all gradients at the batch-start values):
-//   k_det_tensor      one lane per tensor entry: gather the N factor rows,
+// batches; all gradients at the batch-start values), three launches:
+//   k_det_entries     one lane per tensor entry: gather the N factor rows,
 //                     single pass over the core (contract.hpp) -> x~, e,
 //                     w_n; write the row gradients of Eq (8) and the scalar
-//                     -e to a per-batch scratch row
-//   k_det_matrix      one lane per coupled-matrix entry: u.v, e, both row
-//                     gradients of Eq (8)
-//   k_core_partial_mfma / k_core_partial / k_core_partial_cp
-//                     core gradient sum_t (-e_t) u^(1)_t o ... o u^(N)_t
-//                     over a fixed chunk of 256 entries (FP32 matrix cores;
-//                     FP64 VALU; hyper-diagonal core)
+//                     -e to a per-batch scratch row; then the chunk's core
+//                     gradient sum_t (-e_t) u^(1)_t o ... o u^(N)_t over its
+//                     256 entries (FP32 matrix cores, or the hyper-diagonal
+//                     core on the VALU; an FP64 Tucker core takes
+//                     k_core_partial).  Later blocks: one lane per
+//                     coupled-matrix entry (u.v, e, both row gradients)
 //   k_rows_reduce     every touched row's contributions summed in a fixed
 //                     order and applied (-eta * sum, damped): a lane, a
-//                     wavefront or pieces of a workgroup each, by row length
+//                     wavefront or pieces of a workgroup each, by row
+//                     length; its last blocks sum the chunk partials in
+//                     order, add the regulariser and apply the core step
 //   k_rows_finish     the pieces of the longest rows, in order
-//   k_core_apply      sums the chunk partials in order, adds the
-//                     regulariser, applies
 // All reductions have a fixed order, so a det-mode run is bitwise
 // reproducible.
 #pragma once
@@ -253,31 +252,165 @@ S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t 
 
 // ------------------------------------------------------------ det: entries
 
-// One lane per tensor entry of the batch.  Scratch row layout per entry:
+// Coupled-matrix entries of one det batch (every matrix in the same launch).
+template <typename T> struct DetMatrix {
+    const int32_t *ids;       // the batch's sorted item ids of this matrix
+    int64_t n, id_base;       // entries in the batch; item id of entry 0
+    const int32_t *row, *col;
+    const T *val, *Uc, *V;
+    const int32_t *cntV;
+    const T *gy;              // adjoint upstream gradient; null: training
+    T *scr;                   // scratch rows of this matrix
+    int J;
+    int64_t b0;               // first block of this matrix in the launch
+};
+
+template <typename T> struct DetMatArgs {
+    DetMatrix<T> m[kMaxM];
+    int M;
+    T lambda_m, lambda_reg;
+};
+
+// One lane per coupled-matrix entry.  Scratch row: [ g_u (J) | g_v (J) | L_u | L_v ].
+template <typename T>
+S3_DEV void det_matrix_entry(const DetMatrix<T> &d, int64_t s, T lambda_m, T lambda_reg) {
+    const int64_t e = (int64_t)d.ids[s] - d.id_base;
+    const int J = d.J;
+    const T *u = d.Uc + (int64_t)d.row[e] * J;
+    const T *v = d.V + (int64_t)d.col[e] * J;
+    T yh = T(0), uu = T(0), vv = T(0);
+    for (int k = 0; k < J; ++k) {
+        yh = fmaT(u[k], v[k], yh);
+        uu = fmaT(u[k], u[k], uu);
+        vv = fmaT(v[k], v[k], vv);
+    }
+    const bool train = (d.gy == nullptr);
+    // training: d/du = -lm e v, d/dv = -lm e u + lm reg v; adjoint: gy v, gy u
+    const T q = train ? -lambda_m * (d.val[e] - yh) : d.gy[e];
+    const T rv = train ? lambda_m * lambda_reg / (T)d.cntV[d.col[e]] : T(0);
+    T *out = d.scr + s * (2 * J + 2);
+    for (int k = 0; k < J; ++k) {
+        out[k] = q * v[k];
+        out[J + k] = fmaT(q, u[k], rv * v[k]);
+    }
+    out[2 * J] = lambda_m * vv;
+    out[2 * J + 1] = fmaT(lambda_m, uu, rv);
+}
+
+// Core gradient of one 256-entry tile on the FP32 matrix cores:
+//   C[j1][tau] = sum_t (q u^(1))_t[j1] * (u^(2) o ... o u^(N))_t[tau]
+// as a (16 x 256) x (256 x 16 n-tiles) product with v_mfma_f32_16x16x4f32
+// (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 (l / 16) + r][l % 16]
+// in lane l, register r).  M = j1 (JP <= 16, zero padded), K = the tile's
+// entries, N = tail index tau; wave w takes n-tiles w, w + 4, ...; the
+// Khatri-Rao operand is formed from the LDS-staged rows as it is consumed.
+typedef float s3_v4f __attribute__((ext_vector_type(4)));
+
+template <int N, int JP>
+S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
+    constexpr int NW = kChunk / kWave;                    // waves per tile
+    constexpr int TPW = (NT + NW - 1) / NW;              // n-tiles per wave (max)
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int i16 = lane & 15, kq = lane >> 4;
+    s3_v4f acc[TPW];
+    int tj[TPW][N - 1];
+    bool tv[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        acc[q] = s3_v4f{0.f, 0.f, 0.f, 0.f};
+        const int tau = 16 * (wv + NW * q) + i16;
+        tv[q] = (wv + NW * q < NT) && tau < TAIL;
+        int r = tv[q] ? tau : 0;
+#pragma unroll
+        for (int n = N - 2; n >= 0; --n) { tj[q][n] = r % JP; r /= JP; }
+    }
+    for (int k0 = 0; k0 < kChunk; k0 += 4) {
+        const int t = k0 + kq;
+        const float a = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            if (wv + NW * q < NT) {  // uniform over the wave
+                float b = s_u[(t * (N - 1)) * JP + tj[q][0]];
+#pragma unroll
+                for (int n = 1; n < N - 1; ++n) b *= s_u[(t * (N - 1) + n) * JP + tj[q][n]];
+                b = tv[q] ? b : 0.f;
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        if (!(wv + NW * q < NT)) continue;
+        const int tau = 16 * (wv + NW * q) + i16;
+        if (tau >= TAIL) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j1 = 4 * kq + r;
+            if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[q][r];
+        }
+    }
+}
+
+// Whether the det launch also forms each chunk's core-gradient partial (FP32
+// Tucker cores on the matrix cores, hyper-diagonal cores on the VALU); an
+// FP64 Tucker core takes k_core_partial after it.
+template <typename T, int CT> constexpr bool det_fused_core() {
+    return CT == kCP || std::is_same<T, float>::value;
+}
+
+// One det batch's entries in one launch.  Blocks [0, t_blocks): one lane per
+// tensor entry, block b = core chunk b.  Each lane gathers its N factor rows,
+// makes the single pass over the core (contract.hpp) for x~, e and w_n, and
+// writes its scratch row
 //   [ g_1 (JP) | ... | g_N (JP) | L_1 .. L_N | q | L_G ]   (stride N*JP + N + 2)
 // where g_n = q w_n + (lambda_reg / cnt_n) u_n is the Eq (8) row gradient,
 // q = -e (training) or the upstream sensitivity (adjoint), L_n = |w_n|^2 +
-// lambda_reg / cnt_n and L_G = prod_n |u_n|^2 the curvatures.
+// lambda_reg / cnt_n and L_G the entry's core curvature.  With a fused core
+// the rows still in registers then give the chunk's core-gradient partial
+//   P[b][j] = sum_{t in chunk} q_t u^(1)_t[j_1] ... u^(N)_t[j_N]   (padded j)
+// and the chunk's curvature sum, in a fixed order.  Blocks from t_blocks on:
+// one lane per coupled-matrix entry.
 // ADJ = false: training gradients; ADJ = true: adjoint (q = gx[e], no
 // regulariser).  The mode is a template flag and the entry's value is loaded
 // before the contraction: with a run-time choice between two loads after it
 // the compiler front-loads every scalar core load and spills them.
 template <int N, int JP, typename T, bool ADJ, int CT = kReuse>
-__global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32_t *__restrict__ ids,
-                                                    int64_t nt, const T *__restrict__ Gp,
-                                                    T *__restrict__ scr, int64_t stride,
-                                                    const T *__restrict__ gx) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const int32_t *__restrict__ ids,
+                                                        int64_t nt, int64_t t_blocks, const T *__restrict__ Gp,
+                                                        T *__restrict__ scr, int64_t stride,
+                                                        const T *__restrict__ gx, T *__restrict__ part,
+                                                        T *__restrict__ part_curv, DetMatArgs<T> B) {
+    constexpr bool kFuse = det_fused_core<T, CT>();
+    constexpr bool kMfma = kFuse && CT != kCP;
+    __shared__ float s_q[kMfma ? kChunk * JP : 1];
+    __shared__ float s_u[kMfma ? kChunk * (N - 1) * JP : 1];
+    __shared__ T s_red[kChunk / kWave][(kFuse && !kMfma) ? JP + 1 : 1];
+    const int64_t blk = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    if (blk >= t_blocks) {
+        int m = 0;
+        for (int h = 1; h < B.M; ++h)
+            if (blk >= B.m[h].b0) m = h;
+        const DetMatrix<T> &d = B.m[m];
+        const int64_t s = (blk - d.b0) * kChunk + tid;
+        if (s < d.n) det_matrix_entry(d, s, B.lambda_m, B.lambda_reg);
+        return;
+    }
+    const int64_t s = blk * kChunk + tid;
+    T u[N][JP];
+    T q = T(0), curv = T(0);
     if (s < nt) {
         const int64_t e = ids[s];
-        T u[N][JP], w[N][JP];
+        T w[N][JP];
         int32_t rows[N];
         load_rows<N, JP, T>(A, e, u, rows);
         const T xv = ADJ ? gx[e] : A.val[e];
         T xhat;
         contract_any<CT, N, JP, T>(Gp, u, w, xhat);
         constexpr bool train = !ADJ;
-        const T q = train ? -(xv - xhat) : xv;
+        q = train ? -(xv - xhat) : xv;
         // fixed JP stride per mode (padding lanes hold zeros): stores at
         // run-time offsets here also make the compiler spill the core loads
         T *out = scr + s * stride;
@@ -292,48 +425,62 @@ __global__ __launch_bounds__(256) void k_det_tensor(TensorArgs<T> A, const int32
             }
             out[N * JP + n] = ww + reg;
         }
+        curv = core_curv<CT, N, JP, T>(u);
         out[stride - 2] = q;
-        out[stride - 1] = core_curv<CT, N, JP, T>(u);
+        out[stride - 1] = curv;
+    } else {
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int k = 0; k < JP; ++k) u[n][k] = T(0);
     }
-}
-
-// One lane per coupled-matrix entry.  Scratch row: [ g_u (J) | g_v (J) | L_u | L_v ].
-template <typename T>
-__global__ __launch_bounds__(256) void k_det_matrix(const int32_t *__restrict__ ids, int64_t nm,
-                                                    int64_t id_base, const int32_t *__restrict__ row,
-                                                    const int32_t *__restrict__ col,
-                                                    const T *__restrict__ val, const T *__restrict__ Uc,
-                                                    const T *__restrict__ V, int J,
-                                                    const int32_t *__restrict__ cntV, T lambda_m,
-                                                    T lambda_reg, T *__restrict__ scr,
-                                                    const T *__restrict__ gy) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nm) return;
-    const int64_t e = (int64_t)ids[s] - id_base;
-    const T *u = Uc + (int64_t)row[e] * J;
-    const T *v = V + (int64_t)col[e] * J;
-    T yh = T(0), uu = T(0), vv = T(0);
-    for (int k = 0; k < J; ++k) {
-        yh = fmaT(u[k], v[k], yh);
-        uu = fmaT(u[k], u[k], uu);
-        vv = fmaT(v[k], v[k], vv);
+    if constexpr (kMfma) {
+        // stage q u^(1) and the tail rows, then the chunk's MFMA tile
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+#pragma unroll
+        for (int n = 1; n < N; ++n)
+#pragma unroll
+            for (int k = 0; k < JP; ++k) s_u[(tid * (N - 1) + n - 1) * JP + k] = u[n][k];
+        curv = wave_sum(curv);
+        if (lane == 0) s_red[wv][0] = curv;
+        __syncthreads();
+        constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+        core_tile_mfma<N, JP>(s_q, s_u, (float *)part + blk * (JP * TAIL));
+        if (tid == 0) {
+            T c = T(0);
+            for (int x = 0; x < kChunk / kWave; ++x) c += s_red[x][0];
+            part_curv[blk] = c;
+        }
+    } else if constexpr (kFuse) {
+        // hyper-diagonal core: lane t holds q_t prod_n u_n[r] for every r;
+        // the chunk sums go through the wavefronts in order
+#pragma unroll
+        for (int r = 0; r < JP; ++r) {
+            T p = q;
+#pragma unroll
+            for (int n = 0; n < N; ++n) p *= u[n][r];
+            const T t = wave_sum(p);
+            if (lane == 0) s_red[wv][r] = t;
+        }
+        {
+            const T t = wave_sum(curv);
+            if (lane == 0) s_red[wv][JP] = t;
+        }
+        __syncthreads();
+        if (tid <= JP) {
+            T t = T(0);
+            for (int x = 0; x < kChunk / kWave; ++x) t += s_red[x][tid];
+            if (tid < JP) part[blk * JP + tid] = t;
+            else part_curv[blk] = t;
+        }
     }
-    const bool train = (gy == nullptr);
-    // training: d/du = -lm e v, d/dv = -lm e u + lm reg v; adjoint: gy v, gy u
-    const T q = train ? -lambda_m * (val[e] - yh) : gy[e];
-    const T rv = train ? lambda_m * lambda_reg / (T)cntV[col[e]] : T(0);
-    T *out = scr + s * (2 * J + 2);
-    for (int k = 0; k < J; ++k) {
-        out[k] = q * v[k];
-        out[J + k] = fmaT(q, u[k], rv * v[k]);
-    }
-    out[2 * J] = lambda_m * vv;
-    out[2 * J + 1] = fmaT(lambda_m, uu, rv);
 }
 
 // ---------------------------------------------------------- det: core grad
 
-// Core-gradient partial over one chunk of kChunk entries of the batch:
+// FP64 Tucker core-gradient partial over one chunk of kChunk entries of the
+// batch (same sum as the fused FP32 tile, on the VALU):
 //   P[chunk][j] = sum_{t in chunk} q_t u^(1)_t[j_1] ... u^(N)_t[j_N]   (padded j)
 // Thread tau owns one index of modes 2..N and all JP values of mode 1.
 template <int N, int JP, typename T>
@@ -400,207 +547,71 @@ __global__ __launch_bounds__(512) void k_core_partial(TensorArgs<T> A, const int
     if (tid == 0) part_curv[blockIdx.x] = curv;
 }
 
-// Core gradient of one 256-entry tile on the FP32 matrix cores:
-//   C[j1][tau] = sum_t (q u^(1))_t[j1] * (u^(2) o ... o u^(N))_t[tau]
-// as a (16 x 256) x (256 x 16 n-tiles) product with v_mfma_f32_16x16x4f32
-// (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 (l / 16) + r][l % 16]
-// in lane l, register r).  M = j1 (JP <= 16, zero padded), K = the tile's
-// entries, N = tail index tau; wave w takes n-tiles w, w + 4, ...; the
-// Khatri-Rao operand is formed from the LDS-staged rows as it is consumed.
-typedef float s3_v4f __attribute__((ext_vector_type(4)));
+// The batch's core step, run by the last blocks of k_rows_reduce:
+// G[j] -= eta * step, step = (sum_chunks P + nt * reg_core * G) / damp, and
+// the padded copy Gp the next batch contracts with takes the new value;
+// accumulate != 0: dG[j] += sum_chunks P (adjoint, Gp untouched).  One block
+// per 16 padded core elements: lane el of phase ph sums chunks ph, ph + 16,
+// ... of element el (and of the curvature), then the phases are added in
+// order.  A hyper-diagonal core is one padded vector (Nc = 1).
+template <typename T> struct CoreStep {
+    T *G;                       // core, or its gradient in the adjoint
+    T *Gp;                      // zero-padded JP^Nc copy (training only)
+    const T *part, *part_curv;  // chunk partials [nchunks][KP], [nchunks]
+    int64_t nchunks, nt, KP, blocks;
+    int Nc, JP, Js[kMaxN];
+    T reg_core, eta, kappa;
+    int damp, accumulate;
+};
 
-template <int N, int JP>
-S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
-    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
-    constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
-    constexpr int NW = kChunk / kWave;                    // waves per tile
-    constexpr int TPW = (NT + NW - 1) / NW;              // n-tiles per wave (max)
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const int i16 = lane & 15, kq = lane >> 4;
-    s3_v4f acc[TPW];
-    int tj[TPW][N - 1];
-    bool tv[TPW];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        acc[q] = s3_v4f{0.f, 0.f, 0.f, 0.f};
-        const int tau = 16 * (wv + NW * q) + i16;
-        tv[q] = (wv + NW * q < NT) && tau < TAIL;
-        int r = tv[q] ? tau : 0;
-#pragma unroll
-        for (int n = N - 2; n >= 0; --n) { tj[q][n] = r % JP; r /= JP; }
-    }
-    for (int k0 = 0; k0 < kChunk; k0 += 4) {
-        const int t = k0 + kq;
-        const float a = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            if (wv + NW * q < NT) {  // uniform over the wave
-                float b = s_u[(t * (N - 1)) * JP + tj[q][0]];
-#pragma unroll
-                for (int n = 1; n < N - 1; ++n) b *= s_u[(t * (N - 1) + n) * JP + tj[q][n]];
-                b = tv[q] ? b : 0.f;
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        if (!(wv + NW * q < NT)) continue;
-        const int tau = 16 * (wv + NW * q) + i16;
-        if (tau >= TAIL) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j1 = 4 * kq + r;
-            if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[q][r];
-        }
-    }
-}
-
-// FP32 det-mode core partial of one chunk on the matrix cores: the chunk's
-// operands are staged in LDS exactly as the lock-free tile does, and the
-// MFMA accumulation order is fixed, so runs stay bitwise reproducible.
-template <int N, int JP>
-__global__ __launch_bounds__(kChunk) void k_core_partial_mfma(TensorArgs<float> A, const int32_t *__restrict__ ids,
-                                                              int64_t nt, const float *__restrict__ scr,
-                                                              int64_t stride, float *__restrict__ part,
-                                                              float *__restrict__ part_curv) {
-    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
-    __shared__ float s_q[kChunk * JP];
-    __shared__ float s_u[kChunk * (N - 1) * JP];
-    __shared__ float s_c[kChunk / kWave];
-    const int tid = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * kChunk + tid;
-    float curv = 0.f;
-    if (s < nt) {
-        const int64_t e = ids[s];
-        const float q = scr[s * stride + stride - 2];
-        curv = scr[s * stride + stride - 1];
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            const float *r = A.U[n] + (int64_t)A.idx[(int64_t)n * A.nnz + e] * A.J[n];
-#pragma unroll
-            for (int k = 0; k < JP; ++k) {
-                const float v = (k < A.J[n]) ? r[k] : 0.f;
-                if (n == 0) s_q[tid * JP + k] = q * v;
-                else s_u[(tid * (N - 1) + n - 1) * JP + k] = v;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = 0.f;
-#pragma unroll
-        for (int x = 0; x < (N - 1) * JP; ++x) s_u[tid * (N - 1) * JP + x] = 0.f;
-    }
-    curv = wave_sum(curv);
-    if ((tid & (kWave - 1)) == 0) s_c[tid / kWave] = curv;
-    __syncthreads();
-    core_tile_mfma<N, JP>(s_q, s_u, part + (int64_t)blockIdx.x * (JP * TAIL));
-    if (tid == 0) {
-        float c = 0.f;
-        for (int w = 0; w < kChunk / kWave; ++w) c += s_c[w];
-        part_curv[blockIdx.x] = c;
-    }
-}
-
-// Det-mode core partial of one chunk for a hyper-diagonal core: lane t
-// holds q_t prod_n u_n[r] for every r (and the entry's core curvature); the
-// chunk sums go through the wavefronts in order.
-template <int N, int JP, typename T>
-__global__ __launch_bounds__(kChunk) void k_core_partial_cp(TensorArgs<T> A, const int32_t *__restrict__ ids,
-                                                            int64_t nt, const T *__restrict__ scr, int64_t stride,
-                                                            T *__restrict__ part, T *__restrict__ part_curv) {
-    __shared__ T s_red[kChunk / kWave][JP + 1];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const int64_t s = (int64_t)blockIdx.x * kChunk + tid;
-    T c[JP + 1];
-#pragma unroll
-    for (int r = 0; r <= JP; ++r) c[r] = T(0);
-    if (s < nt) {
-        const int64_t e = ids[s];
-        T u[N][JP];
-        int32_t rows[N];
-        load_rows<N, JP, T>(A, e, u, rows);
-        const T q = scr[s * stride + stride - 2];
-#pragma unroll
-        for (int r = 0; r < JP; ++r) {
-            T p = q;
-#pragma unroll
-            for (int n = 0; n < N; ++n) p *= u[n][r];
-            c[r] = p;
-        }
-        c[JP] = scr[s * stride + stride - 1];
-    }
-#pragma unroll
-    for (int r = 0; r <= JP; ++r) {
-        const T t = wave_sum(c[r]);
-        if (lane == 0) s_red[wv][r] = t;
-    }
-    __syncthreads();
-    if (tid <= JP) {
-        T t = T(0);
-        for (int w = 0; w < kChunk / kWave; ++w) t += s_red[w][tid];
-        if (tid < JP) part[(int64_t)blockIdx.x * JP + tid] = t;
-        else part_curv[blockIdx.x] = t;
-    }
-}
-
-// G[j] -= eta * step, step = (sum_chunks P + nt * reg_core * G) / damp;
-// accumulate != 0: dG[j] += sum_chunks P (adjoint).  One block per 16 padded
-// core elements: lane el of phase ph sums chunks ph, ph + 16, ... of element
-// el (and of the curvature), then the phases are added in order.
-template <int N, typename T>
-__global__ __launch_bounds__(256) void k_core_apply(T *__restrict__ G, const T *__restrict__ part,
-                                                    const T *__restrict__ part_curv, int64_t nchunks, int JP,
-                                                    int J0, int J1, int J2, int J3, int64_t nt, T reg_core,
-                                                    T eta, T kappa, int damp, int accumulate, int cp) {
-    __shared__ T s_p[2][16][17];
-    const int Js[4] = {J0, J1, J2, J3};
-    int64_t KP = 1;
-    for (int n = 0; n < (cp ? 1 : N); ++n) KP *= JP;
+template <typename T>
+S3_DEV void core_step_block(const CoreStep<T> &c, int64_t blk, T (&s_p)[2][16][17]) {
     const int el = threadIdx.x & 15, ph = threadIdx.x >> 4;
-    const int64_t pj = (int64_t)blockIdx.x * 16 + el;
+    const int64_t KP = c.KP, nchunks = c.nchunks;
+    const int64_t pj = blk * 16 + el;
     const int64_t pr = pj < KP ? pj : 0;
     T s0 = T(0), s1 = T(0), L0 = T(0), L1 = T(0);
-    int64_t c = ph;
-    for (; c + 16 < nchunks; c += 32) {
-        s0 += part[c * KP + pr];
-        s1 += part[(c + 16) * KP + pr];
-        L0 += part_curv[c];
-        L1 += part_curv[c + 16];
+    int64_t ch = ph;
+    for (; ch + 16 < nchunks; ch += 32) {
+        s0 += c.part[ch * KP + pr];
+        s1 += c.part[(ch + 16) * KP + pr];
+        L0 += c.part_curv[ch];
+        L1 += c.part_curv[ch + 16];
     }
-    for (; c < nchunks; c += 16) {
-        s0 += part[c * KP + pr];
-        L0 += part_curv[c];
+    for (; ch < nchunks; ch += 16) {
+        s0 += c.part[ch * KP + pr];
+        L0 += c.part_curv[ch];
     }
     s_p[0][ph][el] = s0 + s1;
     s_p[1][ph][el] = L0 + L1;
     __syncthreads();
     if (ph != 0 || pj >= KP) return;
     T s = T(0), L = T(0);
-    for (int q = 0; q < 16; ++q) {
-        s += s_p[0][q][el];
-        L += s_p[1][q][el];
+    for (int x = 0; x < 16; ++x) {
+        s += s_p[0][x][el];
+        L += s_p[1][x][el];
     }
-    // padded index -> core index (the padding has no element); a
-    // hyper-diagonal core is one padded vector
+    // padded index -> core index (the padding has no element)
     int64_t rem = pj, j = 0, mul = 1;
-    for (int n = (cp ? 0 : N - 1); n >= 0; --n) {
-        const int jn = (int)(rem % JP);
-        rem /= JP;
-        if (jn >= Js[n]) return;
+    for (int n = c.Nc - 1; n >= 0; --n) {
+        const int jn = (int)(rem % c.JP);
+        rem /= c.JP;
+        if (jn >= c.Js[n]) return;
         j += jn * mul;
-        mul *= Js[n];
+        mul *= c.Js[n];
     }
-    if (accumulate) {
-        G[j] += s;
+    if (c.accumulate) {
+        c.G[j] += s;
     } else {
-        const T g = s + (T)nt * reg_core * G[j];
-        T scale = eta;
-        if (damp) {
-            const T d = kappa * eta * (L + (T)nt * reg_core);
-            scale = eta / (d > T(1) ? d : T(1));
+        const T g = s + (T)c.nt * c.reg_core * c.G[j];
+        T scale = c.eta;
+        if (c.damp) {
+            const T d = c.kappa * c.eta * (L + (T)c.nt * c.reg_core);
+            scale = c.eta / (d > T(1) ? d : T(1));
         }
-        G[j] -= scale * g;
+        const T v = c.G[j] - scale * g;
+        c.G[j] = v;
+        c.Gp[pj] = v;
     }
 }
 
@@ -651,6 +662,7 @@ template <typename T> struct RowsArgs {
     int64_t part_base[kMaxN + kMaxM];
     T eta, kappa;
     int damp, accumulate;
+    CoreStep<T> core;           // blocks [b_end, b_end + core.blocks)
 };
 
 template <typename T>
@@ -671,7 +683,12 @@ S3_DEV void rows_update(T *P, int32_t row, int J, int k, T g, T L, const RowsArg
 template <typename T>
 __global__ __launch_bounds__(kRowsThreads) void k_rows_reduce(RowsArgs<T> a) {
     __shared__ T s_red[kRowsThreads / kWave][kRowsJ + 1];
+    __shared__ T s_p[2][16][17];
     const int64_t blk = blockIdx.x;
+    if (blk >= a.b_end) {
+        core_step_block(a.core, blk - a.b_end, s_p);
+        return;
+    }
     int gi = 0;
     for (int h = 1; h < a.G; ++h)
         if (blk >= a.g[h].b_lane) gi = h;

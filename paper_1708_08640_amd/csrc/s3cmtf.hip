@@ -59,7 +59,8 @@ struct Carver {
 // ------------------------------------------------------------------ dispatch
 
 struct KernelSet {
-    void (*det_tensor)(s3_plan *, const int32_t *, int64_t, const void *, hipStream_t);
+    void (*det_entries)(s3_plan *, const int32_t *, int64_t, int64_t, const void *, const void *, int64_t,
+                        hipStream_t);
     void (*core_partial)(s3_plan *, const int32_t *, int64_t, hipStream_t);
     void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
     void (*predict)(s3_plan *, const int32_t *, int64_t, void *, hipStream_t);
@@ -161,30 +162,31 @@ template <typename T> TensorArgs<T> tensor_args(const s3_plan *p, const int32_t 
 // CT: the per-entry contraction (reuse, naive ablation, or the
 // hyper-diagonal CP core)
 template <int N, int JP, typename T, int CT = kReuse> struct Impl {
-    static void det_tensor(s3_plan *p, const int32_t *ids, int64_t nt, const void *gx, hipStream_t st) {
+    // the batch's tensor entries (t_blocks chunks, 0 when the adjoint has
+    // no tensor sensitivity) and coupled-matrix entries (*mats) in one launch
+    static void det_entries(s3_plan *p, const int32_t *ids, int64_t nt, int64_t t_blocks, const void *gx,
+                            const void *mats, int64_t blocks, hipStream_t st) {
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
+        const DetMatArgs<T> &B = *(const DetMatArgs<T> *)mats;
         if (gx)
-            hipLaunchKernelGGL((k_det_tensor<N, JP, T, true, CT>), dim3(grid_for(nt, 256, 1ll << 30)), dim3(256),
-                               0, st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx);
+            hipLaunchKernelGGL((k_det_entries<N, JP, T, true, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st, a,
+                               ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx,
+                               (T *)p->part, (T *)p->part_curv, B);
         else
-            hipLaunchKernelGGL((k_det_tensor<N, JP, T, false, CT>), dim3(grid_for(nt, 256, 1ll << 30)),
-                               dim3(256), 0, st, a, ids, nt, (const T *)p->Gp, (T *)p->scr, p->t_stride,
-                               (const T *)nullptr);
+            hipLaunchKernelGGL((k_det_entries<N, JP, T, false, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
+                               a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
+                               (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B);
     }
+    // FP64 Tucker core partials (the other cores are formed in det_entries)
     static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
-        constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
-        constexpr int TPB = ((TAIL + 63) / 64) * 64;
-        auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
-        const int64_t nch = (nt + kChunk - 1) / kChunk;
-        if constexpr (CT == kCP)
-            hipLaunchKernelGGL((k_core_partial_cp<N, JP, T>), dim3((unsigned)nch), dim3(kChunk), 0, st, a, ids, nt,
-                               (const T *)p->scr, p->t_stride, (T *)p->part, (T *)p->part_curv);
-        else if constexpr (std::is_same<T, float>::value)
-            hipLaunchKernelGGL((k_core_partial_mfma<N, JP>), dim3((unsigned)nch), dim3(kChunk), 0, st, a, ids, nt,
-                               (const float *)p->scr, p->t_stride, (float *)p->part, (float *)p->part_curv);
-        else
+        if constexpr (!det_fused_core<T, CT>()) {
+            constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+            constexpr int TPB = ((TAIL + 63) / 64) * 64;
+            auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
+            const int64_t nch = (nt + kChunk - 1) / kChunk;
             hipLaunchKernelGGL((k_core_partial<N, JP, T>), dim3((unsigned)nch), dim3(TPB), 0, st, a, ids, nt,
                                (const T *)p->scr, p->t_stride, (T *)p->part, (T *)p->part_curv);
+        }
     }
     static void sq_err(s3_plan *p, const int32_t *idx, const void *val, int64_t nnz, double *part,
                        hipStream_t st) {
@@ -209,7 +211,7 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
 
 template <int N, int JP, typename T, int CT = kReuse> KernelSet make_set() {
     using I = Impl<N, JP, T, CT>;
-    return KernelSet{&I::det_tensor, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor};
+    return KernelSet{&I::det_entries, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor};
 }
 
 // the ablation's kernels exist for the shapes of the tests and of the
@@ -293,7 +295,7 @@ double eta_of(const s3_desc &d, int epoch) { return d.eta0 / (1.0 + d.mu * (doub
 // launch when some row has more than kLongSeg contributions
 template <typename T>
 void rows_apply(s3_plan *p, int64_t b, void *const *P, double eta, double kappa, int damp, int acc,
-                hipStream_t st) {
+                const CoreStep<T> *core, hipStream_t st) {
     RowsArgs<T> a{};
     a.G = p->N + p->M;
     a.scr = (const T *)p->scr;
@@ -336,21 +338,36 @@ void rows_apply(s3_plan *p, int64_t b, void *const *P, double eta, double kappa,
         a.n_long += r.l1 - r.l0;
     }
     a.b_end = blk;
+    if (core) {
+        a.core = *core;
+        blk += core->blocks;
+    }
     if (blk > 0) hipLaunchKernelGGL(k_rows_reduce<T>, dim3((unsigned)blk), dim3(kRowsThreads), 0, st, a);
     if (a.n_long > 0)
         hipLaunchKernelGGL(k_rows_finish<T>, dim3((unsigned)((a.n_long * kWave + kRowsThreads - 1) / kRowsThreads)),
                            dim3(kRowsThreads), 0, st, a);
 }
 
-template <typename T>
-void core_apply(s3_plan *p, int64_t nt, double eta, int acc, void *dst, hipStream_t st) {
-    const int64_t nch = (nt + kChunk - 1) / kChunk;
-    const double reg_core = p->d.lambda_reg / (double)p->nX;
-    const int *J = p->d.rank;
-    auto kern = (p->N == 3) ? k_core_apply<3, T> : k_core_apply<4, T>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)((p->KP + 15) / 16)), dim3(256), 0, st, (T *)dst, (const T *)p->part,
-                       (const T *)p->part_curv, nch, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1, nt,
-                       (T)reg_core, (T)eta, (T)(p->N + 1), p->d.damping, acc, p->d.core_kind == S3_CORE_CP ? 1 : 0);
+// the core step of a batch of nt tensor entries (run by k_rows_reduce)
+template <typename T> CoreStep<T> core_step(s3_plan *p, int64_t nt, double eta, bool acc, void *dst) {
+    CoreStep<T> c{};
+    c.G = (T *)dst;
+    c.Gp = acc ? nullptr : (T *)p->Gp;
+    c.part = (const T *)p->part;
+    c.part_curv = (const T *)p->part_curv;
+    c.nchunks = (nt + kChunk - 1) / kChunk;
+    c.nt = nt;
+    c.KP = p->KP;
+    c.blocks = (p->KP + 15) / 16;
+    c.Nc = p->d.core_kind == S3_CORE_CP ? 1 : p->N;
+    c.JP = p->JP;
+    for (int n = 0; n < kMaxN; ++n) c.Js[n] = n < p->N ? p->d.rank[n] : 1;
+    c.reg_core = (T)(p->d.lambda_reg / (double)p->nX);
+    c.eta = (T)eta;
+    c.kappa = (T)(p->N + 1);
+    c.damp = p->d.damping;
+    c.accumulate = acc ? 1 : 0;
+    return c;
 }
 
 template <typename T> void pad_core(s3_plan *p, hipStream_t st) {
@@ -366,7 +383,11 @@ template <typename T> void fill(void *ptr, int64_t n, double v, hipStream_t st) 
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, (T *)ptr, n, (T)v);
 }
 
-// One det-mode batch.  gx/gy non-null: adjoint pass (accumulate into dU/dG/dV).
+// One det-mode batch.  gx/gy non-null: adjoint pass (accumulate into
+// dU/dG/dV).  Launches: the batch's entries (and, except for an FP64 Tucker
+// core, its chunk core partials), then the row sums with the core step in the
+// same launch, then the longest rows' pieces.  The padded core copy Gp must
+// be current on entry; the training core step keeps it so.
 template <typename T>
 void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *const *gy, void *const *dU,
                void *dG, void *const *dV, hipStream_t st) {
@@ -374,38 +395,52 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
     const bool adj = (gx != nullptr) || (gy != nullptr) || (dG != nullptr);
     const int64_t *to = p->h_type_off.data() + b * (M + 1);
     const int64_t t0 = to[0], nt = to[1] - to[0];
-    pad_core<T>(p, st);
-    if (nt > 0) {
-        if (adj && gx == nullptr) {
-            fill<T>(p->scr, nt * p->t_stride, 0.0, st);
-        } else {
-            const bool prof = p->prof && !adj;
-            if (prof) (void)prof_mark(p, p->pev_used++, st);
-            p->ks.det_tensor(p, p->sorted_ids + t0, nt, gx, st);
-            if (prof) (void)prof_mark(p, p->pev_used++, st);
-        }
-    }
+    // the adjoint without a tensor (or a matrix) sensitivity contributes zeros
+    const bool t_zero = adj && gx == nullptr;
+    if (nt > 0 && t_zero) fill<T>(p->scr, nt * p->t_stride, 0.0, st);
+    DetMatArgs<T> B{};
+    B.M = M;
+    B.lambda_m = (T)p->d.lambda_m;
+    B.lambda_reg = (T)p->d.lambda_reg;
+    const int64_t t_blocks = (nt > 0 && !t_zero) ? (nt + kChunk - 1) / kChunk : 0;
+    int64_t blocks = t_blocks;
     for (int m = 0; m < M; ++m) {
         const int64_t m0 = to[m + 1], nm = to[m + 2] - to[m + 1];
-        if (nm <= 0) continue;
         T *scr = (T *)p->scr + p->m_base[m];
         const int c = p->d.mat_mode[m];
+        DetMatrix<T> &d = B.m[m];
+        d.b0 = blocks;
+        if (nm <= 0) continue;
         if (adj && (gy == nullptr || gy[m] == nullptr)) {
             fill<T>(scr, nm * p->m_stride[m], 0.0, st);
             continue;
         }
-        hipLaunchKernelGGL(k_det_matrix<T>, dim3(grid_for(nm, 256, 1ll << 30)), dim3(256), 0, st,
-                           p->sorted_ids + m0, nm, p->mat_begin[m], p->b.y_row[m], p->b.y_col[m],
-                           (const T *)p->b.y_val[m], (const T *)p->b.U[c], (const T *)p->b.V[m],
-                           p->d.rank[c], p->cntV[m], (T)p->d.lambda_m, (T)p->d.lambda_reg, scr,
-                           adj ? (const T *)gy[m] : (const T *)nullptr);
+        d.ids = p->sorted_ids + m0;
+        d.n = nm;
+        d.id_base = p->mat_begin[m];
+        d.row = p->b.y_row[m];
+        d.col = p->b.y_col[m];
+        d.val = (const T *)p->b.y_val[m];
+        d.Uc = (const T *)p->b.U[c];
+        d.V = (const T *)p->b.V[m];
+        d.cntV = p->cntV[m];
+        d.gy = adj ? (const T *)gy[m] : nullptr;
+        d.scr = scr;
+        d.J = p->d.rank[c];
+        blocks += (nm + kChunk - 1) / kChunk;
     }
-    if (nt > 0) p->ks.core_partial(p, p->sorted_ids + t0, nt, st);
+    if (blocks > 0) {
+        const bool prof = p->prof && !adj;
+        if (prof) (void)prof_mark(p, p->pev_used++, st);
+        p->ks.det_entries(p, p->sorted_ids + t0, nt, t_blocks, adj ? gx : nullptr, &B, blocks, st);
+        if (prof) (void)prof_mark(p, p->pev_used++, st);
+    }
+    if (t_blocks > 0) p->ks.core_partial(p, p->sorted_ids + t0, nt, st);
     void *P[S3_MAX_ORDER + S3_MAX_MATRICES];
     for (int g = 0; g < p->N + M; ++g)
         P[g] = (g < p->N) ? (adj ? dU[g] : p->b.U[g]) : (adj ? dV[g - p->N] : p->b.V[g - p->N]);
-    rows_apply<T>(p, b, P, eta, (double)(p->N + 1), p->d.damping, adj ? 1 : 0, st);
-    if (nt > 0) core_apply<T>(p, nt, eta, adj ? 1 : 0, adj ? dG : p->b.G, st);
+    const CoreStep<T> core = core_step<T>(p, nt, eta, adj, adj ? dG : p->b.G);
+    rows_apply<T>(p, b, P, eta, (double)(p->N + 1), p->d.damping, adj ? 1 : 0, t_blocks > 0 ? &core : nullptr, st);
 }
 
 template <typename T> size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz,
@@ -956,6 +991,9 @@ s3_status s3_det_batches(s3_plan *p, int64_t first, int64_t count, double eta, v
         return fail(p, S3_ERR_INVALID_ARG, "batch range [%lld, %lld) outside [0, %lld)", (long long)first,
                     (long long)(first + count), (long long)p->n_batches);
     hipStream_t st = (hipStream_t)stream;
+    // the caller may have written G since the last call: pad it once, and
+    // every batch's core step keeps the padded copy current
+    if (count > 0) p->tsize == 8 ? pad_core<double>(p, st) : pad_core<float>(p, st);
     for (int64_t b = first; b < first + count; ++b) {
         if (p->tsize == 8) det_batch<double>(p, b, eta, nullptr, nullptr, nullptr, nullptr, nullptr, st);
         else det_batch<float>(p, b, eta, nullptr, nullptr, nullptr, nullptr, nullptr, st);
@@ -1078,6 +1116,7 @@ s3_status s3_backward(s3_plan *p, const void *gx, const void *const *gy, void *c
     }
     const void *const nogy[S3_MAX_MATRICES] = {nullptr, nullptr, nullptr, nullptr};
     const void *const *gyv = gy ? gy : nogy;
+    f64 ? pad_core<double>(p, st) : pad_core<float>(p, st);
     for (int64_t b = 0; b < p->n_batches; ++b) {
         if (f64) det_batch<double>(p, b, 0.0, gx, gyv, dU, dG, dV, st);
         else det_batch<float>(p, b, 0.0, gx, gyv, dU, dG, dV, st);
