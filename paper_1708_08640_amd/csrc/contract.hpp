@@ -84,6 +84,72 @@ S3_DEV void contract4(GP G, const T (&a)[JP], const T (&b)[JP], const T (&c)[JP]
     xhat = x;
 }
 
+// The single pass above split over S workers by the first core index:
+// worker w (uniform over its wavefront) takes j1 = w, w + S, ... -- a[i]
+// holds u^(1)[w + S i] and v the other modes' rows -- and returns w_1 at its
+// j1, its partial sums of w_2 .. w_N over those j1, and its part of
+// x~ = sum_j1 u^(1)[j1] w_1[j1].  The S partials added in a fixed order give
+// the single pass's results (up to the order of the additions).
+template <int N, int JP, int S, typename T>
+S3_DEV void contract_part(const T *__restrict__ G, int w, const T (&a)[(JP + S - 1) / S],
+                          const T (&v)[N - 1][JP], T (&w1)[(JP + S - 1) / S], T (&wv)[N - 1][JP],
+                          T &xpart) {
+    constexpr int NI = (JP + S - 1) / S;
+#pragma unroll
+    for (int n = 0; n < N - 1; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; ++k) wv[n][k] = T(0);
+    T x = T(0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        w1[i] = T(0);
+        const int j1 = w + S * i;
+        if (j1 >= JP) continue;  // uniform
+        T s1 = T(0);
+        if constexpr (N == 3) {
+            const T *Gj = G + j1 * JP * JP;
+#pragma unroll
+            for (int j2 = 0; j2 < JP; ++j2) {
+                const T ab = a[i] * v[0][j2];
+                T t = T(0);
+#pragma unroll
+                for (int j3 = 0; j3 < JP; ++j3) {
+                    const T g = Gj[j2 * JP + j3];
+                    t = fmaT(g, v[1][j3], t);
+                    wv[1][j3] = fmaT(ab, g, wv[1][j3]);
+                }
+                wv[0][j2] = fmaT(a[i], t, wv[0][j2]);
+                s1 = fmaT(v[0][j2], t, s1);
+            }
+        } else {
+            const T *Gj = G + j1 * JP * JP * JP;
+#pragma unroll
+            for (int j2 = 0; j2 < JP; ++j2) {
+                const T ab = a[i] * v[0][j2];
+                T s2 = T(0);
+#pragma unroll
+                for (int j3 = 0; j3 < JP; ++j3) {
+                    const T abc = ab * v[1][j3];
+                    T t = T(0);
+#pragma unroll
+                    for (int j4 = 0; j4 < JP; ++j4) {
+                        const T g = Gj[(j2 * JP + j3) * JP + j4];
+                        t = fmaT(g, v[2][j4], t);
+                        wv[2][j4] = fmaT(abc, g, wv[2][j4]);
+                    }
+                    wv[1][j3] = fmaT(ab, t, wv[1][j3]);
+                    s2 = fmaT(v[1][j3], t, s2);
+                }
+                wv[0][j2] = fmaT(a[i], s2, wv[0][j2]);
+                s1 = fmaT(v[0][j2], s2, s1);
+            }
+        }
+        w1[i] = s1;
+        x = fmaT(a[i], s1, x);
+    }
+    xpart = x;
+}
+
 // N-generic front end: rows u[n][k], outputs w[n][k]
 template <int N, int JP, typename T, typename GP>
 S3_DEV void contract(GP G, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {

@@ -2,12 +2,13 @@
 //
 // Hot path of one deterministic mini-batch step (item order cut into
 // batches; all gradients at the batch-start values), three launches:
-//   k_det_entries     one lane per tensor entry: gather the N factor rows,
+//   k_det_entries     per tensor entry (one lane, or a quarter of the core
+//                     on each of four wavefronts): gather the N factor rows,
 //                     single pass over the core (contract.hpp) -> x~, e,
 //                     w_n; write the row gradients of Eq (8) and the scalar
 //                     -e to a per-batch scratch row; then the chunk's core
 //                     gradient sum_t (-e_t) u^(1)_t o ... o u^(N)_t over its
-//                     256 entries (FP32 matrix cores, or the hyper-diagonal
+//                     64 or 256 entries (FP32 matrix cores, or the hyper-diagonal
 //                     core on the VALU; an FP64 Tucker core takes
 //                     k_core_partial).  Later blocks: one lane per
 //                     coupled-matrix entry (u.v, e, both row gradients)
@@ -272,26 +273,42 @@ template <typename T> struct DetMatArgs {
 };
 
 // One lane per coupled-matrix entry.  Scratch row: [ g_u (J) | g_v (J) | L_u | L_v ].
+// The rows are read with the largest rank unrolled and predicated, so all
+// their loads are in flight at once.
 template <typename T>
 S3_DEV void det_matrix_entry(const DetMatrix<T> &d, int64_t s, T lambda_m, T lambda_reg) {
+    constexpr int JM = 16;  // largest rank
     const int64_t e = (int64_t)d.ids[s] - d.id_base;
     const int J = d.J;
-    const T *u = d.Uc + (int64_t)d.row[e] * J;
-    const T *v = d.V + (int64_t)d.col[e] * J;
+    const int32_t col = d.col[e];
+    const T *pu = d.Uc + (int64_t)d.row[e] * J;
+    const T *pv = d.V + (int64_t)col * J;
+    const T y = d.gy ? d.gy[e] : d.val[e];
+    const T cv = d.gy ? T(0) : (T)d.cntV[col];
+    T u[JM], v[JM];
+#pragma unroll
+    for (int k = 0; k < JM; ++k) {
+        u[k] = k < J ? pu[k] : T(0);
+        v[k] = k < J ? pv[k] : T(0);
+    }
     T yh = T(0), uu = T(0), vv = T(0);
-    for (int k = 0; k < J; ++k) {
+#pragma unroll
+    for (int k = 0; k < JM; ++k) {
         yh = fmaT(u[k], v[k], yh);
         uu = fmaT(u[k], u[k], uu);
         vv = fmaT(v[k], v[k], vv);
     }
     const bool train = (d.gy == nullptr);
     // training: d/du = -lm e v, d/dv = -lm e u + lm reg v; adjoint: gy v, gy u
-    const T q = train ? -lambda_m * (d.val[e] - yh) : d.gy[e];
-    const T rv = train ? lambda_m * lambda_reg / (T)d.cntV[d.col[e]] : T(0);
+    const T q = train ? -lambda_m * (y - yh) : y;
+    const T rv = train ? lambda_m * lambda_reg / cv : T(0);
     T *out = d.scr + s * (2 * J + 2);
-    for (int k = 0; k < J; ++k) {
-        out[k] = q * v[k];
-        out[J + k] = fmaT(q, u[k], rv * v[k]);
+#pragma unroll
+    for (int k = 0; k < JM; ++k) {
+        if (k < J) {
+            out[k] = q * v[k];
+            out[J + k] = fmaT(q, u[k], rv * v[k]);
+        }
     }
     out[2 * J] = lambda_m * vv;
     out[2 * J + 1] = fmaT(lambda_m, uu, rv);
@@ -299,18 +316,19 @@ S3_DEV void det_matrix_entry(const DetMatrix<T> &d, int64_t s, T lambda_m, T lam
 
 // Core gradient of one 256-entry tile on the FP32 matrix cores:
 //   C[j1][tau] = sum_t (q u^(1))_t[j1] * (u^(2) o ... o u^(N))_t[tau]
-// as a (16 x 256) x (256 x 16 n-tiles) product with v_mfma_f32_16x16x4f32
+// (K = 256 entries, or 64 in the split det form) as a (16 x K) x (K x 16
+// n-tiles) product with v_mfma_f32_16x16x4f32
 // (A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, D[4 (l / 16) + r][l % 16]
 // in lane l, register r).  M = j1 (JP <= 16, zero padded), K = the tile's
 // entries, N = tail index tau; wave w takes n-tiles w, w + 4, ...; the
 // Khatri-Rao operand is formed from the LDS-staged rows as it is consumed.
 typedef float s3_v4f __attribute__((ext_vector_type(4)));
 
-template <int N, int JP>
+template <int N, int JP, int K = kChunk>
 S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
     constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
-    constexpr int NW = kChunk / kWave;                    // waves per tile
+    constexpr int NW = kChunk / kWave;                    // waves of the 256-thread block
     constexpr int TPW = (NT + NW - 1) / NW;              // n-tiles per wave (max)
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int i16 = lane & 15, kq = lane >> 4;
@@ -326,7 +344,7 @@ S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
 #pragma unroll
         for (int n = N - 2; n >= 0; --n) { tj[q][n] = r % JP; r /= JP; }
     }
-    for (int k0 = 0; k0 < kChunk; k0 += 4) {
+    for (int k0 = 0; k0 < K; k0 += 4) {
         const int t = k0 + kq;
         const float a = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
 #pragma unroll
@@ -360,44 +378,166 @@ template <typename T, int CT> constexpr bool det_fused_core() {
     return CT == kCP || std::is_same<T, float>::value;
 }
 
-// One det batch's entries in one launch.  Blocks [0, t_blocks): one lane per
-// tensor entry, block b = core chunk b.  Each lane gathers its N factor rows,
-// makes the single pass over the core (contract.hpp) for x~, e and w_n, and
-// writes its scratch row
-//   [ g_1 (JP) | ... | g_N (JP) | L_1 .. L_N | q | L_G ]   (stride N*JP + N + 2)
-// where g_n = q w_n + (lambda_reg / cnt_n) u_n is the Eq (8) row gradient,
-// q = -e (training) or the upstream sensitivity (adjoint), L_n = |w_n|^2 +
-// lambda_reg / cnt_n and L_G the entry's core curvature.  With a fused core
-// the rows still in registers then give the chunk's core-gradient partial
-//   P[b][j] = sum_{t in chunk} q_t u^(1)_t[j_1] ... u^(N)_t[j_N]   (padded j)
-// and the chunk's curvature sum, in a fixed order.  Blocks from t_blocks on:
-// one lane per coupled-matrix entry.
-// ADJ = false: training gradients; ADJ = true: adjoint (q = gx[e], no
-// regulariser).  The mode is a template flag and the entry's value is loaded
-// before the contraction: with a run-time choice between two loads after it
-// the compiler front-loads every scalar core load and spills them.
-template <int N, int JP, typename T, bool ADJ, int CT = kReuse>
-__global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const int32_t *__restrict__ ids,
-                                                        int64_t nt, int64_t t_blocks, const T *__restrict__ Gp,
-                                                        T *__restrict__ scr, int64_t stride,
-                                                        const T *__restrict__ gx, T *__restrict__ part,
-                                                        T *__restrict__ part_curv, DetMatArgs<T> B) {
+// Whether the FP32 reuse contraction of a det block is split over its four
+// wavefronts (64 entries per block; see det_tensor_split), and the entries per
+// block and core chunk either way.
+template <typename T, int CT> constexpr bool det_split() {
+    return CT == kReuse && std::is_same<T, float>::value;
+}
+template <typename T, int CT> constexpr int det_chunk() { return det_split<T, CT>() ? kWave : kChunk; }
+
+// Tensor entries of one det block, FP32 reuse contraction: the block's 64
+// entries are contracted by all four wavefronts at once, wavefront w taking
+// the core slices j1 = w, w + 4, ... (contract_part), so a batch spreads
+// over four times as many wavefronts, each with a quarter of the serial
+// work.  The partial w_2 .. w_N, x~, |w_1|^2 and |u^(1)|^2 meet in LDS and
+// are added in wavefront order; wavefront w writes g_1 at its j1,
+// wavefront n (1 <= n < N) the summed w_(n+1)'s row gradient g_(n+1) and
+// curvature, wavefront 0 also L_1, q and L_G.  The rows then give the
+// block's 64-entry core chunk on the matrix cores.  Same scratch row as the
+// one-lane form below.
+template <int N, int JP, bool ADJ>
+S3_DEV void det_tensor_split(const TensorArgs<float> &A, const int32_t *__restrict__ ids, int64_t nt,
+                             const float *__restrict__ Gp, float *__restrict__ scr, int64_t stride,
+                             const float *__restrict__ gx, float *__restrict__ part, float *__restrict__ part_curv,
+                             int64_t blk) {
+    using T = float;
+    constexpr int S = kChunk / kWave, E = kWave, NI = (JP + S - 1) / S;
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    __shared__ float s_wp[S * (N - 1) * JP * E];  // [worker][mode - 2][k][entry]
+    __shared__ float s_m[S * 3 * E];              // [worker][x~, |w_1|^2, |u^(1)|^2][entry]
+    __shared__ float s_q[E * JP];
+    __shared__ float s_u[E * (N - 1) * JP];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t s = blk * E + lane;
+    const bool live = s < nt;
+    T a[NI], v[N - 1][JP], w1[NI], wv[N - 1][JP];
+    T xp = T(0), xv = T(0);
+    int32_t rows[N];
+    if (live) {
+        const int64_t e = ids[s];
+#pragma unroll
+        for (int n = 0; n < N; ++n) rows[n] = A.idx[(int64_t)n * A.nnz + e];
+        const T *r0 = A.U[0] + (int64_t)rows[0] * A.J[0];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int j1 = w + S * i;
+            a[i] = (j1 < A.J[0]) ? r0[j1] : T(0);
+        }
+#pragma unroll
+        for (int n = 1; n < N; ++n) {
+            const T *r = A.U[n] + (int64_t)rows[n] * A.J[n];
+#pragma unroll
+            for (int k = 0; k < JP; ++k) v[n - 1][k] = (k < A.J[n]) ? r[k] : T(0);
+        }
+        xv = ADJ ? gx[e] : A.val[e];
+        contract_part<N, JP, S, T>(Gp, w, a, v, w1, wv, xp);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) a[i] = w1[i] = T(0);
+#pragma unroll
+        for (int n = 0; n < N - 1; ++n)
+#pragma unroll
+            for (int k = 0; k < JP; ++k) v[n][k] = wv[n][k] = T(0);
+#pragma unroll
+        for (int n = 0; n < N; ++n) rows[n] = 0;
+    }
+    T w1sq = T(0), a2 = T(0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        w1sq = fmaT(w1[i], w1[i], w1sq);
+        a2 = fmaT(a[i], a[i], a2);
+    }
+#pragma unroll
+    for (int n = 0; n < N - 1; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_wp[((w * (N - 1) + n) * JP + k) * E + lane] = wv[n][k];
+    s_m[(w * 3 + 0) * E + lane] = xp;
+    s_m[(w * 3 + 1) * E + lane] = w1sq;
+    s_m[(w * 3 + 2) * E + lane] = a2;
+    __syncthreads();
+    T xhat = s_m[lane];
+#pragma unroll
+    for (int x = 1; x < S; ++x) xhat += s_m[x * 3 * E + lane];
+    const T q = ADJ ? xv : -(xv - xhat);
+    T curv = T(0);
+    if (live) {
+        T *out = scr + s * stride;
+        const T reg0 = ADJ ? T(0) : A.lambda_reg / (T)A.cnt[0][rows[0]];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int j1 = w + S * i;
+            if (j1 < JP) out[j1] = fmaT(q, w1[i], reg0 * a[i]);
+        }
+#pragma unroll
+        for (int n = 1; n < N; ++n) {
+            if (w != n) continue;  // uniform
+            const T regn = ADJ ? T(0) : A.lambda_reg / (T)A.cnt[n][rows[n]];
+            T ww = T(0);
+#pragma unroll
+            for (int k = 0; k < JP; ++k) {
+                T t = s_wp[((n - 1) * JP + k) * E + lane];
+#pragma unroll
+                for (int x = 1; x < S; ++x) t += s_wp[((x * (N - 1) + n - 1) * JP + k) * E + lane];
+                out[n * JP + k] = fmaT(q, t, regn * v[n - 1][k]);
+                ww = fmaT(t, t, ww);
+            }
+            out[N * JP + n] = ww + regn;
+        }
+        if (w == 0) {
+            T l1 = s_m[E + lane], uu0 = s_m[2 * E + lane];
+#pragma unroll
+            for (int x = 1; x < S; ++x) {
+                l1 += s_m[(x * 3 + 1) * E + lane];
+                uu0 += s_m[(x * 3 + 2) * E + lane];
+            }
+            out[N * JP] = l1 + reg0;
+            curv = uu0;
+#pragma unroll
+            for (int n = 1; n < N; ++n) {
+                T uu = T(0);
+#pragma unroll
+                for (int k = 0; k < JP; ++k) uu = fmaT(v[n - 1][k], v[n - 1][k], uu);
+                curv *= uu;
+            }
+            out[stride - 2] = q;
+            out[stride - 1] = curv;
+        }
+    }
+    // the chunk's curvature sum, and its core gradient on the matrix cores
+    if (w == 0) {
+        curv = wave_sum(curv);
+        if (lane == 0) part_curv[blk] = curv;
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int j1 = w + S * i;
+        if (j1 < JP) s_q[lane * JP + j1] = q * a[i];
+    }
+#pragma unroll
+    for (int n = 1; n < N; ++n) {
+        if (w != n) continue;  // uniform
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_u[(lane * (N - 1) + n - 1) * JP + k] = v[n - 1][k];
+    }
+    __syncthreads();
+    core_tile_mfma<N, JP, E>(s_q, s_u, part + blk * (JP * TAIL));
+}
+
+// The one-lane form (FP64, the naive ablation and the hyper-diagonal core):
+// block blk = entries [256 blk, 256 blk + 256) = core chunk blk.
+template <int N, int JP, typename T, bool ADJ, int CT>
+S3_DEV void det_tensor_lane(const TensorArgs<T> &A, const int32_t *__restrict__ ids, int64_t nt,
+                            const T *__restrict__ Gp, T *__restrict__ scr, int64_t stride,
+                            const T *__restrict__ gx, T *__restrict__ part, T *__restrict__ part_curv,
+                            int64_t blk) {
     constexpr bool kFuse = det_fused_core<T, CT>();
-    constexpr bool kMfma = kFuse && CT != kCP;
+    constexpr bool kMfma = kFuse && CT != kCP && !det_split<T, CT>();
     __shared__ float s_q[kMfma ? kChunk * JP : 1];
     __shared__ float s_u[kMfma ? kChunk * (N - 1) * JP : 1];
     __shared__ T s_red[kChunk / kWave][(kFuse && !kMfma) ? JP + 1 : 1];
-    const int64_t blk = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    if (blk >= t_blocks) {
-        int m = 0;
-        for (int h = 1; h < B.M; ++h)
-            if (blk >= B.m[h].b0) m = h;
-        const DetMatrix<T> &d = B.m[m];
-        const int64_t s = (blk - d.b0) * kChunk + tid;
-        if (s < d.n) det_matrix_entry(d, s, B.lambda_m, B.lambda_reg);
-        return;
-    }
     const int64_t s = blk * kChunk + tid;
     T u[N][JP];
     T q = T(0), curv = T(0);
@@ -475,6 +615,47 @@ __global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const i
             else part_curv[blk] = t;
         }
     }
+}
+
+// One det batch's entries in one launch.  Blocks [0, t_blocks): the tensor
+// entries, block b = core chunk b (64 entries contracted by the block's four
+// wavefronts together for the FP32 reuse contraction, det_tensor_split; else
+// 256 entries, one lane each, det_tensor_lane).  Each entry's N factor rows
+// are gathered, the single pass over the core (contract.hpp) gives x~, e and
+// w_n, and the entry's scratch row is written:
+//   [ g_1 (JP) | ... | g_N (JP) | L_1 .. L_N | q | L_G ]   (stride N*JP + N + 2)
+// where g_n = q w_n + (lambda_reg / cnt_n) u_n is the Eq (8) row gradient,
+// q = -e (training) or the upstream sensitivity (adjoint), L_n = |w_n|^2 +
+// lambda_reg / cnt_n and L_G the entry's core curvature.  With a fused core
+// the rows still in registers then give the chunk's core-gradient partial
+//   P[b][j] = sum_{t in chunk} q_t u^(1)_t[j_1] ... u^(N)_t[j_N]   (padded j)
+// and the chunk's curvature sum, in a fixed order.  Blocks from t_blocks on:
+// one lane per coupled-matrix entry.
+// ADJ = false: training gradients; ADJ = true: adjoint (q = gx[e], no
+// regulariser).  The mode is a template flag and the entry's value is loaded
+// before the contraction: with a run-time choice between two loads after it
+// the compiler front-loads every scalar core load and spills them.
+template <int N, int JP, typename T, bool ADJ, int CT = kReuse>
+__global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const int32_t *__restrict__ ids,
+                                                        int64_t nt, int64_t t_blocks, const T *__restrict__ Gp,
+                                                        T *__restrict__ scr, int64_t stride,
+                                                        const T *__restrict__ gx, T *__restrict__ part,
+                                                        T *__restrict__ part_curv, DetMatArgs<T> B) {
+    const int64_t blk = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (blk >= t_blocks) {
+        int m = 0;
+        for (int h = 1; h < B.M; ++h)
+            if (blk >= B.m[h].b0) m = h;
+        const DetMatrix<T> &d = B.m[m];
+        const int64_t s = (blk - d.b0) * kChunk + tid;
+        if (s < d.n) det_matrix_entry(d, s, B.lambda_m, B.lambda_reg);
+        return;
+    }
+    if constexpr (det_split<T, CT>())
+        det_tensor_split<N, JP, ADJ>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);
+    else
+        det_tensor_lane<N, JP, T, ADJ, CT>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);
 }
 
 // ---------------------------------------------------------- det: core grad
@@ -626,15 +807,16 @@ S3_DEV void core_step_block(const CoreStep<T> &c, int64_t blk, T (&s_p)[2][16][1
 //   wave blocks   one wavefront per segment of up to kLongSeg (bind-time
 //                 list): lanes stride the list, then a fixed butterfly;
 //   piece blocks  the longer segments cut into pieces of kPiece
-//                 contributions (bind-time list), one workgroup each (four
-//                 contributions per lane, two loads in flight), whose
+//                 contributions (bind-time list), one workgroup each (two
+//                 contributions per lane, both loads in flight), whose
 //                 sums k_rows_finish adds in piece order and applies (a
 //                 single head row would otherwise run on one CU).
 // All groups (factor matrices and coupled factors) of the batch go in the
-// same two launches.
+// same two launches.  The thresholds are the fastest of a sweep on the
+// 10M-entry Zipf(1.2) workload (batches of 65,536).
 constexpr int64_t kShortSeg = 8;
-constexpr int64_t kLongSeg = 512;
-constexpr int64_t kPiece = 1024;
+constexpr int64_t kLongSeg = 128;
+constexpr int64_t kPiece = 512;
 constexpr int kRowsThreads = 256;
 constexpr int kRowsJ = 16;  // largest rank
 
@@ -655,7 +837,7 @@ struct RowsGroup {
 template <typename T> struct RowsArgs {
     RowsGroup g[kMaxN + kMaxM];
     int G;
-    int64_t b_end;              // blocks of k_rows_reduce
+    int64_t b_end;              // row blocks of k_rows_reduce
     int64_t n_long;             // long segments of the batch over all groups
     const T *scr;
     T *part;                    // piece sums [piece][kRowsJ + 1], pieces numbered across groups
@@ -705,18 +887,31 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_reduce(RowsArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < kRowsJ; ++k) acc[k] = T(0);
         T L = T(0);
-        // every contribution index first, then the rows: two round trips
+        // every contribution index first, then the rows four at a time with
+        // predicated loads (all four in flight), added in contribution order
         uint64_t v[kShortSeg];
 #pragma unroll
         for (int i = 0; i < kShortSeg; ++i) v[i] = (c0 + i < c1) ? g.contrib[c0 + i] : 0;
+        constexpr int kGrp = 4;
 #pragma unroll
-        for (int i = 0; i < kShortSeg; ++i) {
-            if (c0 + i >= c1) break;
-            const T *gr = a.scr + (int64_t)(v[i] & 0xffffffffull);
+        for (int h = 0; h < kShortSeg; h += kGrp) {
+            if (c0 + h >= c1) break;
+            T r[kGrp][kRowsJ], l[kGrp];
 #pragma unroll
-            for (int k = 0; k < kRowsJ; ++k)
-                if (k < J) acc[k] += gr[k];
-            L += a.scr[(int64_t)(v[i] >> 32)];
+            for (int i = 0; i < kGrp; ++i) {
+                const bool ok = c0 + h + i < c1;
+                const T *gr = a.scr + (int64_t)(v[h + i] & 0xffffffffull);
+#pragma unroll
+                for (int k = 0; k < kRowsJ; ++k) r[i][k] = (ok && k < J) ? gr[k] : T(0);
+                l[i] = ok ? a.scr[(int64_t)(v[h + i] >> 32)] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < kGrp; ++i) {
+#pragma unroll
+                for (int k = 0; k < kRowsJ; ++k)
+                    if (k < J) acc[k] += r[i][k];
+                L += l[i];
+            }
         }
         const int32_t row = g.seg_row[s];
 #pragma unroll
@@ -816,9 +1011,20 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_finish(RowsArgs<T> a) {
     const int64_t li = g.l0 + w;
     const int J = g.J;
     if (lane > J) return;
+    // the pieces in order, four loads in flight
+    const T *pp = a.part + (a.part_base[gi] - g.p0) * (kRowsJ + 1) + (lane < J ? lane : kRowsJ);
+    const int64_t q1 = g.long_fp[li + 1];
+    int64_t pc = g.long_fp[li];
     T t = T(0);
-    for (int64_t pc = g.long_fp[li]; pc < g.long_fp[li + 1]; ++pc)
-        t += a.part[(a.part_base[gi] + pc - g.p0) * (kRowsJ + 1) + (lane < J ? lane : kRowsJ)];
+    for (; pc + 3 < q1; pc += 4) {
+        const T x0 = pp[pc * (kRowsJ + 1)], x1 = pp[(pc + 1) * (kRowsJ + 1)];
+        const T x2 = pp[(pc + 2) * (kRowsJ + 1)], x3 = pp[(pc + 3) * (kRowsJ + 1)];
+        t += x0;
+        t += x1;
+        t += x2;
+        t += x3;
+    }
+    for (; pc < q1; ++pc) t += pp[pc * (kRowsJ + 1)];
     const T L = __shfl(t, J, kWave);
     if (lane < J) rows_update((T *)g.P, g.seg_row[g.long_ids[li]], J, lane, t, L, a);
 }

@@ -65,6 +65,7 @@ struct KernelSet {
     void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
     void (*predict)(s3_plan *, const int32_t *, int64_t, void *, hipStream_t);
     void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t);
+    int det_chunk;  // tensor entries per det block and core chunk
 };
 
 struct s3_plan {
@@ -211,7 +212,8 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
 
 template <int N, int JP, typename T, int CT = kReuse> KernelSet make_set() {
     using I = Impl<N, JP, T, CT>;
-    return KernelSet{&I::det_entries, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor};
+    return KernelSet{&I::det_entries, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor,
+                     det_chunk<T, CT>()};
 }
 
 // the ablation's kernels exist for the shapes of the tests and of the
@@ -355,7 +357,7 @@ template <typename T> CoreStep<T> core_step(s3_plan *p, int64_t nt, double eta, 
     c.Gp = acc ? nullptr : (T *)p->Gp;
     c.part = (const T *)p->part;
     c.part_curv = (const T *)p->part_curv;
-    c.nchunks = (nt + kChunk - 1) / kChunk;
+    c.nchunks = (nt + p->ks.det_chunk - 1) / p->ks.det_chunk;
     c.nt = nt;
     c.KP = p->KP;
     c.blocks = (p->KP + 15) / 16;
@@ -402,7 +404,7 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
     B.M = M;
     B.lambda_m = (T)p->d.lambda_m;
     B.lambda_reg = (T)p->d.lambda_reg;
-    const int64_t t_blocks = (nt > 0 && !t_zero) ? (nt + kChunk - 1) / kChunk : 0;
+    const int64_t t_blocks = (nt > 0 && !t_zero) ? (nt + p->ks.det_chunk - 1) / p->ks.det_chunk : 0;
     int64_t blocks = t_blocks;
     for (int m = 0; m < M; ++m) {
         const int64_t m0 = to[m + 1], nm = to[m + 2] - to[m + 1];
@@ -647,7 +649,7 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
             off += std::min(B, std::max<int64_t>(y_nnz[m], 1)) * p->m_stride[m];
         }
         p->scr = c.take<T>((size_t)off);
-        p->max_chunks = (max_nt + kChunk - 1) / kChunk;
+        p->max_chunks = (max_nt + p->ks.det_chunk - 1) / p->ks.det_chunk;
         p->part = c.take<T>((size_t)(p->max_chunks * p->KP));
         p->part_curv = c.take<T>((size_t)p->max_chunks);
         // piece sums of one batch: every group's contributions in pieces,
