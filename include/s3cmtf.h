@@ -259,8 +259,9 @@ s3_status s3_orthogonalize(s3_plan *plan, void *stream);
 s3_status s3_sync_bf16(s3_plan *plan, void *stream);
 
 /* Turn per-launch timing of the dominant kernel (the tensor-entry kernel of
- * the epoch's mode) on or off; off by default.  When on, s3_epoch records a
- * pair of HIP events around each such launch on the epoch's stream.        */
+ * the epoch's mode) on or off; off by default.  When on, each such launch
+ * carries a pair of timing-only HIP events (no system-scope fence) that the
+ * dispatch itself stamps at its start and end (hipExtLaunchKernelGGL).     */
 s3_status s3_set_profiling(s3_plan *plan, int32_t on);
 
 /* After s3_epoch: with profiling on, the summed duration in milliseconds of

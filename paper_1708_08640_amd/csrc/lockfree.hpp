@@ -30,6 +30,7 @@
 // needs the same treatment for its head rows, or thousands of concurrent
 // stale updates of one row overshoot.
 #pragma once
+#include <hip/hip_ext.h>
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -844,7 +845,7 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
 
 template <int N, int JP, typename T, bool EXACT, int CT = kReuse>
 void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
-                            T eta, hipStream_t st) {
+                            T eta, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
     LFMatArgs<T> Y{};
     Y.M = s.M;
@@ -877,8 +878,9 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
     const size_t W = (size_t)JP + 1;
     const size_t smem = std::max((size_t)N * (s.H * W + kTile * W) + 2 * (kTile / kWave),
                                  (size_t)2 * (s.H * W + kTile * W)) * sizeof(T);
-    hipLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile), smem, st, A, Gp, L, Y,
-                       count, eta, (T)(N + 1));
+    // e0/e1 (profiling, may be null) take the dispatch's own start and end
+    hipExtLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile), (uint32_t)smem, st,
+                          e0, e1, 0, A, Gp, L, Y, count, eta, (T)(N + 1));
 }
 
 inline uint64_t splitmix64(uint64_t &x) {

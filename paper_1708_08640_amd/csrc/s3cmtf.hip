@@ -60,11 +60,11 @@ struct Carver {
 
 struct KernelSet {
     void (*det_entries)(s3_plan *, const int32_t *, int64_t, int64_t, const void *, const void *, int64_t,
-                        hipStream_t);
+                        hipStream_t, hipEvent_t, hipEvent_t);
     void (*core_partial)(s3_plan *, const int32_t *, int64_t, hipStream_t);
     void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
     void (*predict)(s3_plan *, const int32_t *, int64_t, void *, hipStream_t);
-    void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t);
+    void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t, hipEvent_t, hipEvent_t);
     int det_chunk;  // tensor entries per det block and core chunk
 };
 
@@ -164,19 +164,20 @@ template <typename T> TensorArgs<T> tensor_args(const s3_plan *p, const int32_t 
 // hyper-diagonal CP core)
 template <int N, int JP, typename T, int CT = kReuse> struct Impl {
     // the batch's tensor entries (t_blocks chunks, 0 when the adjoint has
-    // no tensor sensitivity) and coupled-matrix entries (*mats) in one launch
+    // no tensor sensitivity) and coupled-matrix entries (*mats) in one launch;
+    // e0/e1 (profiling, may be null) take the dispatch's own start and end
     static void det_entries(s3_plan *p, const int32_t *ids, int64_t nt, int64_t t_blocks, const void *gx,
-                            const void *mats, int64_t blocks, hipStream_t st) {
+                            const void *mats, int64_t blocks, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
         const DetMatArgs<T> &B = *(const DetMatArgs<T> *)mats;
         if (gx)
-            hipLaunchKernelGGL((k_det_entries<N, JP, T, true, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st, a,
-                               ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride, (const T *)gx,
-                               (T *)p->part, (T *)p->part_curv, B);
+            hipExtLaunchKernelGGL((k_det_entries<N, JP, T, true, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
+                                  e0, e1, 0, a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
+                                  (const T *)gx, (T *)p->part, (T *)p->part_curv, B);
         else
-            hipLaunchKernelGGL((k_det_entries<N, JP, T, false, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
-                               a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
-                               (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B);
+            hipExtLaunchKernelGGL((k_det_entries<N, JP, T, false, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
+                                  e0, e1, 0, a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
+                                  (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B);
     }
     // FP64 Tucker core partials (the other cores are formed in det_entries)
     static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
@@ -200,13 +201,14 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
         hipLaunchKernelGGL((k_predict<N, JP, T, CT>), dim3(grid_for(nnz, 256, 1ll << 30)), dim3(256), 0, st, a,
                            (const T *)p->Gp, (T *)out);
     }
-    static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st) {
+    static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
         if (p->exact)
             lockfree_tensor_launch<N, JP, T, true, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                                          (const T *)p->Gp, first, count, (T)eta, st);
+                                                          (const T *)p->Gp, first, count, (T)eta, st, e0, e1);
         else
             lockfree_tensor_launch<N, JP, T, false, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                                           (const T *)p->Gp, first, count, (T)eta, st);
+                                                           (const T *)p->Gp, first, count, (T)eta, st, e0, e1);
     }
 };
 
@@ -279,15 +281,19 @@ int padded_rank(int N, int Jmax) {
     return 0;
 }
 
-// event pair k around a dominant-kernel launch (profiling only)
-hipError_t prof_mark(s3_plan *p, size_t k, hipStream_t st) {
+// profiling event k (created on first use): the pairs 2i, 2i + 1 take the
+// start and end of the i-th dominant-kernel dispatch of an epoch, stamped by
+// the dispatch itself (hipExtLaunchKernelGGL), so they time the kernel alone.
+// They are timing-only events without the system-scope fence, whose cache
+// write-back would otherwise land in the timed interval and slow the next
+// kernel; the epoch's end event, waited on before they are read, has it.
+hipEvent_t prof_event(s3_plan *p, size_t k) {
     while (p->pev.size() <= k) {
         hipEvent_t e;
-        hipError_t r = hipEventCreate(&e);
-        if (r != hipSuccess) return r;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
         p->pev.push_back(e);
     }
-    return hipEventRecord(p->pev[k], st);
+    return p->pev[k];
 }
 
 double eta_of(const s3_desc &d, int epoch) { return d.eta0 / (1.0 + d.mu * (double)epoch); }
@@ -432,10 +438,14 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
         blocks += (nm + kChunk - 1) / kChunk;
     }
     if (blocks > 0) {
-        const bool prof = p->prof && !adj;
-        if (prof) (void)prof_mark(p, p->pev_used++, st);
-        p->ks.det_entries(p, p->sorted_ids + t0, nt, t_blocks, adj ? gx : nullptr, &B, blocks, st);
-        if (prof) (void)prof_mark(p, p->pev_used++, st);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (p->prof && !adj) {
+            e0 = prof_event(p, p->pev_used);
+            e1 = prof_event(p, p->pev_used + 1);
+            if (e0 && e1) p->pev_used += 2;
+            else e0 = e1 = nullptr;
+        }
+        p->ks.det_entries(p, p->sorted_ids + t0, nt, t_blocks, adj ? gx : nullptr, &B, blocks, st, e0, e1);
     }
     if (t_blocks > 0) p->ks.core_partial(p, p->sorted_ids + t0, nt, st);
     void *P[S3_MAX_ORDER + S3_MAX_MATRICES];
@@ -1028,9 +1038,14 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
         s3_status s;
         p->pev_used = 0;
         auto round = [&](int64_t f, int64_t c, double e, hipStream_t s_) {
-            if (p->prof && c > 0) (void)prof_mark(p, p->pev_used++, s_);
-            p->ks.lf_tensor(p, f, c, e, s_);
-            if (p->prof && c > 0) (void)prof_mark(p, p->pev_used++, s_);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (p->prof && c > 0) {
+                e0 = prof_event(p, p->pev_used);
+                e1 = prof_event(p, p->pev_used + 1);
+                if (e0 && e1) p->pev_used += 2;
+                else e0 = e1 = nullptr;
+            }
+            p->ks.lf_tensor(p, f, c, e, s_, e0, e1);
         };
         if (p->tsize == 8) {
             pad_core<double>(p, st);

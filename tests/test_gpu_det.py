@@ -41,6 +41,30 @@ def test_det_batches_match_oracle(name, dtype, batch, damping):
         compare_params(plan, ref, TOL[dtype], f"batch {b}")
 
 
+# FP32 det blocks split the reuse contraction over their four wavefronts
+# (wavefront w takes the core slices j1 = w, w + 4, ...): every padded rank
+# the library has, with ragged ranks (padding inside the slices, and
+# wavefronts with fewer slices than others) and batches whose tensor part is
+# not a whole number of 64-entry blocks.
+SPLIT_CASES = [
+    ("cfg2_slice", (3, 2, 3)), ("cfg2_slice", (4, 4, 3)), ("cfg2_slice", (7, 8, 5)),
+    ("cfg2_slice", (10, 9, 10)), ("cfg2_slice", (11, 12, 12)), ("cfg2_slice", (16, 13, 16)),
+    ("cfg5_slice", (2, 2, 1, 2)), ("cfg5_slice", (4, 3, 4, 4)), ("cfg5_slice", (8, 8, 7, 8)),
+]
+
+
+@pytest.mark.parametrize("name,ranks", SPLIT_CASES, ids=[f"{c[0]}-{'x'.join(map(str, c[1]))}" for c in SPLIT_CASES])
+def test_det_split_contraction_every_padded_rank(name, ranks):
+    print(f"\n[det-split] {name} ranks={ranks}", flush=True)
+    batch = 1000
+    cfg, p, plan, ref, order = setup(name, "f32", batch, True, ranks=ranks)
+    eta = 0.01
+    for b in range(2):
+        plan.det_batches(b, 1, eta)
+        oracle.minibatch_epoch(ref, p, order, batch, eta, b, 1, damping=True)
+        compare_params(plan, ref, TOL["f32"], f"{ranks} batch {b}")
+
+
 # The plain sum rule diverges on Zipf(1.2) data at large batches (a batch
 # sums thousands of gradients of one head row), in the oracle as well, so the
 # undamped whole-epoch case uses a small batch.
