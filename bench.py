@@ -236,7 +236,13 @@ def main():
         "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_entries",
         "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
-        "traffic": profiled_traffic("k_lf_tensor") if args.mode == "lockfree" and cfg.name == "cfg2_zipf_10m" else None,
+        # counters were taken for the default launch only (lock-free, reuse
+        # contraction, Tucker core, 10M-entry workload, rounds of 524,288
+        # items, 64 hot rows)
+        "traffic": profiled_traffic("k_lf_tensor") if (args.mode == "lockfree" and cfg.name == "cfg2_zipf_10m"
+                                                       and args.contraction == "reuse" and args.core == "tucker"
+                                                       and args.round_items == 524288 and args.hot_rows == 64)
+        else None,
         "flops_per_tensor_entry": tensor_entry_flops(cfg.ranks),
         "flops_per_matrix_entry": matrix_entry_flops(cfg.ranks[cfg.matrices[0].mode]) if cfg.matrices else None,
         "launches": launches,
