@@ -253,6 +253,20 @@ s3_status s3_export(s3_plan *plan, int32_t which, int32_t index, double *host_ds
  * partly transformed.  Synchronous.                                        */
 s3_status s3_orthogonalize(s3_plan *plan, void *stream);
 
+/* Fill every bound parameter (U^(n), G, V_m) with independent N(0, sigma^2)
+ * values on the device, the random initialisation of Algorithm 1; callers
+ * may instead write their own initial values into the buffers they bound.
+ * Counter-based: value 2i (and 2i + 1) of parameter q (q = n for U^(n),
+ * N for G, N + 1 + m for V_m) is the Box-Muller pair, in FP64, of the 53-bit
+ * uniforms of counters key_q + 2i and key_q + 2i + 1 passed through
+ * SplitMix64's output function, with key_q = that function applied to
+ * seed + (q + 1) * 0x9E3779B97F4A7C15 (u1 = (bits + 1) 2^-53 in (0, 1], u2 =
+ * bits 2^-53 in [0, 1); element 2i = sigma sqrt(-2 ln u1) cos(2 pi u2),
+ * element 2i + 1 the same with sin).  The result does not depend on the
+ * launch shape.  Needs s3_bind (else S3_ERR_STATE); sigma must be finite and
+ * >= 0 (else S3_ERR_INVALID_ARG).  Asynchronous on stream.                 */
+s3_status s3_init_params(s3_plan *plan, uint64_t seed, double sigma, void *stream);
+
 /* Reserved for bf16 working copies of float masters.  This library has no
  * bf16 mode (S3_BF16 plans are rejected), so it always returns
  * S3_ERR_UNSUPPORTED (S3_ERR_INVALID_ARG for a null plan).                 */

@@ -1166,6 +1166,35 @@ __global__ void k_fill(T *__restrict__ p, int64_t n, T v) {
         p[i] = v;
 }
 
+// SplitMix64's output function (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014; the mixing constants of
+// Vigna's splitmix64): a bijective mix of a 64-bit counter.
+S3_DEV uint64_t splitmix64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// n values N(0, sigma^2) from a counter-based generator: pair i takes the
+// 53-bit uniforms of counters key + 2i and key + 2i + 1 (u1 in (0, 1], u2 in
+// [0, 1)) through the Box-Muller transform, in FP64: elements 2i and 2i + 1
+// are sigma sqrt(-2 ln u1) times cos and sin of 2 pi u2.
+template <typename T>
+__global__ void k_init_normal(T *__restrict__ p, int64_t n, uint64_t key, double sigma) {
+    const int64_t pairs = (n + 1) / 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pairs;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = splitmix64_mix(key + 2 * (uint64_t)i);
+        const uint64_t b = splitmix64_mix(key + 2 * (uint64_t)i + 1);
+        const double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53;
+        const double u2 = (double)(b >> 11) * 0x1.0p-53;
+        const double r = sigma * sqrt(-2.0 * log(u1));
+        const double t = 6.283185307179586 * u2;
+        p[2 * i] = (T)(r * cos(t));
+        if (2 * i + 1 < n) p[2 * i + 1] = (T)(r * sin(t));
+    }
+}
+
 template <typename T>
 __global__ void k_to_f64(const T *__restrict__ src, double *__restrict__ dst, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;

@@ -1210,6 +1210,13 @@ template <typename T> s3_status orthogonalize_impl(s3_plan *p, hipStream_t st) {
     if (bad) return fail(p, S3_ERR_NONFINITE, "orthogonalisation: a factor matrix is not numerically full rank");
     return S3_OK;
 }
+// SplitMix64's output function on the host (same definition as the device
+// one in kernels.hpp), to derive each parameter's counter key
+uint64_t host_splitmix64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
 }  // namespace
 
 extern "C" {
@@ -1224,6 +1231,30 @@ s3_status s3_orthogonalize(s3_plan *p, void *stream) {
             return fail(p, S3_ERR_UNSUPPORTED, "orthogonalisation needs J_n <= min(16, I_n)");
     hipStream_t st = (hipStream_t)stream;
     return p->tsize == 8 ? orthogonalize_impl<double>(p, st) : orthogonalize_impl<float>(p, st);
+}
+
+s3_status s3_init_params(s3_plan *p, uint64_t seed, double sigma, void *stream) {
+    if (!p || !(sigma >= 0.0) || !std::isfinite(sigma)) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_init_params before s3_bind");
+    hipStream_t st = (hipStream_t)stream;
+    // parameter q: U^(n) is q = n, G is q = N, V_m is q = N + 1 + m; its
+    // counters start at the SplitMix64 mix of seed + (q + 1) * golden gamma
+    auto one = [&](void *ptr, int64_t count, int q) {
+        if (count <= 0) return;
+        const uint64_t key = host_splitmix64_mix(seed + 0x9E3779B97F4A7C15ull * (uint64_t)(q + 1));
+        const int64_t pairs = (count + 1) / 2;
+        if (p->tsize == 8)
+            hipLaunchKernelGGL(k_init_normal<double>, dim3(grid_for(pairs, 256, 4096)), dim3(256), 0, st,
+                               (double *)ptr, count, key, sigma);
+        else
+            hipLaunchKernelGGL(k_init_normal<float>, dim3(grid_for(pairs, 256, 4096)), dim3(256), 0, st,
+                               (float *)ptr, count, key, sigma);
+    };
+    for (int n = 0; n < p->N; ++n) one(p->b.U[n], p->d.dims[n] * p->d.rank[n], n);
+    one(p->b.G, p->K, p->N);
+    for (int m = 0; m < p->M; ++m) one(p->b.V[m], p->d.mat_cols[m] * p->d.rank[p->d.mat_mode[m]], p->N + 1 + m);
+    HIPCHK(p, hipGetLastError());
+    return S3_OK;
 }
 
 s3_status s3_sync_bf16(s3_plan *p, void *stream) {

@@ -220,6 +220,12 @@ class S3Plan:
         V <- V R^T (predictions unchanged)."""
         check(self.lib.s3_orthogonalize(self.h, _stream()), self.h)
 
+    def init_params(self, seed: int, sigma: float = 0.1) -> None:
+        """Fill U, G and V with N(0, sigma^2) values on the device
+        (counter-based; see s3_init_params)."""
+        check(self.lib.s3_init_params(self.h, C.c_uint64(int(seed) & (2 ** 64 - 1)), float(sigma), _stream()),
+              self.h)
+
     def params_numpy(self):
         return ([self.export("U", n) for n in range(len(self.U))], self.export("G"),
                 [self.export("V", m) for m in range(len(self.V))])
