@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--hot-rows", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--core", default="tucker", choices=["tucker", "cp"],
-                    help="cp: the hyper-diagonal core (the CP special case), judged against the HBM roof")
+                    help="cp: the hyper-diagonal core (the CP special case), measured against the HBM roof")
     ap.add_argument("--contraction", default="reuse", choices=["reuse", "naive"],
                     help="naive: the per-entry contraction without reuse of partial products (ablation)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)

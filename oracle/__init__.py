@@ -20,7 +20,7 @@ Every function here cites the part of the paper it follows:
 * ``adjoint``             -- transpose of the prediction map (Eq 4 and u.v)
 * ``qr_orthogonalize``    -- Algorithm 1's closing QR step
 
-Parity status of each function is listed in the design doc; none is unpinned.
+Every function is pinned by tests/test_oracle.py; none is parity unpinned.
 """
 from .api import (  # noqa: F401
     Params,

@@ -21,7 +21,7 @@
  *   item ids        0..nX-1 are training tensor entries; then matrix 0's
  *                   entries, matrix 1's entries, ... in order.
  *
- * Readings where the paper is silent or inconsistent (restated in the design doc):
+ * Readings where the paper is silent or inconsistent:
  *   - core regulariser per tensor entry is (lambda_reg / |Omega_X|) G, the
  *     form of Eq (8) and Algorithm 2 (the efficient-gradient lemma drops the
  *     1/|Omega_X| factor, which would make it disagree with the objective);

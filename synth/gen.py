@@ -7,7 +7,7 @@ datasets are not available here; the configurations below stand in for them
 with the same kind of structure: power-law (bounded Zipf) mode indices,
 integer ratings 1-5, coupled matrices sharing one tensor mode.
 
-Recipe (also restated in the design doc):
+Recipe:
 
 * Mode indices: bounded Zipf, P(rank r) proportional to r^-s for r = 1..I,
   sampled by inverse CDF, then mapped rank -> index through a seeded
