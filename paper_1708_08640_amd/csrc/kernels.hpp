@@ -251,14 +251,52 @@ S3_DEV void load_rows(const TensorArgs<T> &A, int64_t e, T (&u)[N][JP], int32_t 
     }
 }
 
+// ----------------------------------------------------- det: batch-ordered items
+
+// Bind time: every item's indices and value copied into the det item order
+// (position p holds item sorted_ids[p]), so the batch kernels read them
+// contiguously instead of through the id: a tensor item's N mode indices go
+// to bidx[n][p] and its value to bval[p]; a matrix item's row and column to
+// bidx[0][p] and bidx[1][p] and its value to bval[p].
+template <typename T> struct GatherArgs {
+    const int32_t *ids;
+    int64_t n, nX;
+    int N, M;
+    const int32_t *x_idx;  // [N][nX]
+    const T *x_val;
+    int64_t mat_begin[kMaxM];
+    const int32_t *y_row[kMaxM], *y_col[kMaxM];
+    const T *y_val[kMaxM];
+    int32_t *bidx;  // [N][n]
+    T *bval;        // [n]
+};
+
+template <typename T> __global__ void k_gather_items(GatherArgs<T> a) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t id = a.ids[p];
+        if (id < a.nX) {
+            for (int n = 0; n < a.N; ++n) a.bidx[(int64_t)n * a.n + p] = a.x_idx[(int64_t)n * a.nX + id];
+            a.bval[p] = a.x_val[id];
+        } else {
+            int m = 0;
+            for (int h = 1; h < a.M; ++h)
+                if (id >= a.mat_begin[h]) m = h;
+            const int64_t e = id - a.mat_begin[m];
+            a.bidx[p] = a.y_row[m][e];
+            a.bidx[a.n + p] = a.y_col[m][e];
+            a.bval[p] = a.y_val[m][e];
+        }
+    }
+}
+
 // ------------------------------------------------------------ det: entries
 
 // Coupled-matrix entries of one det batch (every matrix in the same launch).
 template <typename T> struct DetMatrix {
     const int32_t *ids;       // the batch's sorted item ids of this matrix
     int64_t n, id_base;       // entries in the batch; item id of entry 0
-    const int32_t *row, *col;
-    const T *val, *Uc, *V;
+    const int32_t *row, *col; // the batch's rows and columns, in item order
+    const T *val, *Uc, *V;    // the batch's values, in item order
     const int32_t *cntV;
     const T *gy;              // adjoint upstream gradient; null: training
     T *scr;                   // scratch rows of this matrix
@@ -278,12 +316,11 @@ template <typename T> struct DetMatArgs {
 template <typename T>
 S3_DEV void det_matrix_entry(const DetMatrix<T> &d, int64_t s, T lambda_m, T lambda_reg) {
     constexpr int JM = 16;  // largest rank
-    const int64_t e = (int64_t)d.ids[s] - d.id_base;
     const int J = d.J;
-    const int32_t col = d.col[e];
-    const T *pu = d.Uc + (int64_t)d.row[e] * J;
+    const int32_t col = d.col[s];
+    const T *pu = d.Uc + (int64_t)d.row[s] * J;
     const T *pv = d.V + (int64_t)col * J;
-    const T y = d.gy ? d.gy[e] : d.val[e];
+    const T y = d.gy ? d.gy[(int64_t)d.ids[s] - d.id_base] : d.val[s];
     const T cv = d.gy ? T(0) : (T)d.cntV[col];
     T u[JM], v[JM];
 #pragma unroll
@@ -400,7 +437,8 @@ template <int N, int JP, bool ADJ>
 S3_DEV void det_tensor_split(const TensorArgs<float> &A, const int32_t *__restrict__ ids, int64_t nt,
                              const float *__restrict__ Gp, float *__restrict__ scr, int64_t stride,
                              const float *__restrict__ gx, float *__restrict__ part, float *__restrict__ part_curv,
-                             int64_t blk) {
+                             int64_t blk, const int32_t *__restrict__ bidx, const float *__restrict__ bval,
+                             int64_t bstride) {
     using T = float;
     constexpr int S = kChunk / kWave, E = kWave, NI = (JP + S - 1) / S;
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
@@ -416,9 +454,10 @@ S3_DEV void det_tensor_split(const TensorArgs<float> &A, const int32_t *__restri
     T xp = T(0), xv = T(0);
     int32_t rows[N];
     if (live) {
-        const int64_t e = ids[s];
+        // indices and value in item order (bidx/bval start at the batch's
+        // first tensor item); the id is needed only for the adjoint's input
 #pragma unroll
-        for (int n = 0; n < N; ++n) rows[n] = A.idx[(int64_t)n * A.nnz + e];
+        for (int n = 0; n < N; ++n) rows[n] = bidx[(int64_t)n * bstride + s];
         const T *r0 = A.U[0] + (int64_t)rows[0] * A.J[0];
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
@@ -431,7 +470,7 @@ S3_DEV void det_tensor_split(const TensorArgs<float> &A, const int32_t *__restri
 #pragma unroll
             for (int k = 0; k < JP; ++k) v[n - 1][k] = (k < A.J[n]) ? r[k] : T(0);
         }
-        xv = ADJ ? gx[e] : A.val[e];
+        xv = ADJ ? gx[ids[s]] : bval[s];
         contract_part<N, JP, S, T>(Gp, w, a, v, w1, wv, xp);
     } else {
 #pragma unroll
@@ -640,7 +679,9 @@ __global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const i
                                                         int64_t nt, int64_t t_blocks, const T *__restrict__ Gp,
                                                         T *__restrict__ scr, int64_t stride,
                                                         const T *__restrict__ gx, T *__restrict__ part,
-                                                        T *__restrict__ part_curv, DetMatArgs<T> B) {
+                                                        T *__restrict__ part_curv, DetMatArgs<T> B,
+                                                        const int32_t *__restrict__ bidx,
+                                                        const T *__restrict__ bval, int64_t bstride) {
     const int64_t blk = blockIdx.x;
     const int tid = threadIdx.x;
     if (blk >= t_blocks) {
@@ -653,7 +694,7 @@ __global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const i
         return;
     }
     if constexpr (det_split<T, CT>())
-        det_tensor_split<N, JP, ADJ>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);
+        det_tensor_split<N, JP, ADJ>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk, bidx, bval, bstride);
     else
         det_tensor_lane<N, JP, T, ADJ, CT>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);
 }

@@ -91,6 +91,8 @@ struct s3_plan {
     int64_t y_nnz[S3_MAX_MATRICES] = {};
     int64_t mat_begin[S3_MAX_MATRICES] = {};
     int32_t *sorted_ids = nullptr;
+    int32_t *bidx = nullptr;  // items' indices in det item order [N][n_items]
+    void *bval = nullptr;     // items' values in det item order [n_items]
     std::vector<int64_t> h_type_off;
     Group grp[S3_MAX_ORDER + S3_MAX_MATRICES];
     void *scr = nullptr;
@@ -170,14 +172,17 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
                             const void *mats, int64_t blocks, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
         auto a = tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX);
         const DetMatArgs<T> &B = *(const DetMatArgs<T> *)mats;
+        const int64_t t0 = ids - p->sorted_ids;  // the batch's first tensor item position
+        const int32_t *bidx = p->bidx + t0;
+        const T *bval = (const T *)p->bval + t0;
         if (gx)
             hipExtLaunchKernelGGL((k_det_entries<N, JP, T, true, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
                                   e0, e1, 0, a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
-                                  (const T *)gx, (T *)p->part, (T *)p->part_curv, B);
+                                  (const T *)gx, (T *)p->part, (T *)p->part_curv, B, bidx, bval, p->n_items);
         else
             hipExtLaunchKernelGGL((k_det_entries<N, JP, T, false, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
                                   e0, e1, 0, a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
-                                  (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B);
+                                  (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B, bidx, bval, p->n_items);
     }
     // FP64 Tucker core partials (the other cores are formed in det_entries)
     static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
@@ -426,9 +431,9 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
         d.ids = p->sorted_ids + m0;
         d.n = nm;
         d.id_base = p->mat_begin[m];
-        d.row = p->b.y_row[m];
-        d.col = p->b.y_col[m];
-        d.val = (const T *)p->b.y_val[m];
+        d.row = p->bidx + m0;                // item order
+        d.col = p->bidx + p->n_items + m0;
+        d.val = (const T *)p->bval + m0;
         d.Uc = (const T *)p->b.U[c];
         d.V = (const T *)p->b.V[m];
         d.cntV = p->cntV[m];
@@ -626,6 +631,8 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
     p->qr_G = c.take<T>((size_t)p->K);
     if (with_order) {
         p->sorted_ids = c.take<int32_t>((size_t)n_items);
+        p->bidx = c.take<int32_t>((size_t)N * n_items);
+        p->bval = c.take<T>((size_t)n_items);
         // groups
         for (int g = 0; g < N + M; ++g) {
             int64_t nv = 0;
@@ -704,6 +711,26 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
     const int64_t nkeys = nb * (M + 1);
     hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, key_out, n,
                        nkeys, type_off);
+    {
+        // indices and values in item order for the batch kernels
+        GatherArgs<T> ga{};
+        ga.ids = p->sorted_ids;
+        ga.n = n;
+        ga.nX = p->nX;
+        ga.N = N;
+        ga.M = M;
+        ga.x_idx = p->b.x_idx;
+        ga.x_val = (const T *)p->b.x_val;
+        for (int m = 0; m < M; ++m) {
+            ga.mat_begin[m] = p->mat_begin[m];
+            ga.y_row[m] = p->b.y_row[m];
+            ga.y_col[m] = p->b.y_col[m];
+            ga.y_val[m] = (const T *)p->b.y_val[m];
+        }
+        ga.bidx = p->bidx;
+        ga.bval = (T *)p->bval;
+        hipLaunchKernelGGL(k_gather_items<T>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, ga);
+    }
     p->h_type_off.assign((size_t)nkeys + 1, 0);
     HIPCHK(p, hipMemcpyAsync(p->h_type_off.data(), type_off, sizeof(int64_t) * (nkeys + 1),
                              hipMemcpyDeviceToHost, st));
