@@ -1,25 +1,29 @@
 """Build the gfx950 shared library ``libs3cmtf.so`` from ``csrc/`` with hipcc.
 
 Usage: ``python -m paper_1708_08640_amd.build`` (or ``build()`` from Python).
-The library is written in-tree next to this file.
+The host entry points and each group of kernel sets are separate translation
+units, compiled in parallel and linked into one library written in-tree next
+to this file.
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libs3cmtf.so")
-SOURCES = ["s3cmtf.hip"]
-HEADERS = ["common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp"]
+SOURCES = ["s3cmtf.hip", "sets_f32_3.hip", "sets_f32_4.hip", "sets_f64.hip", "sets_cp.hip",
+           "sets_naive.hip"]
+HEADERS = ["common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "qr.hpp", "plan.hpp"]
 ARCH = os.environ.get("S3_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
     # no packed-FP32 instructions in device code
@@ -34,15 +38,31 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 into the in-tree shared library."""
+    """Compile every HIP source for gfx950 and link the in-tree shared library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".o.tmp" + tag) for s in SOURCES]
+
+    def compile_one(i):
+        cmd = [hipcc, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", "-o", objs[i], os.path.join(CSRC, SOURCES[i])]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    try:
+        with ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(compile_one, range(len(SOURCES))))
+        tmp = LIB + ".tmp" + tag
+        cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

@@ -21,7 +21,7 @@
 // All reductions have a fixed order, so a det-mode run is bitwise
 // reproducible.
 #pragma once
-#include <hipcub/block/block_radix_sort.hpp>
+#include <hipcub/hipcub.hpp>
 
 #include <cstdint>
 
@@ -46,7 +46,7 @@ template <typename T> struct TensorArgs {
 
 // ----------------------------------------------------------------------- prep
 
-__global__ void k_check_range(const int32_t *__restrict__ idx, int64_t n, int64_t limit,
+static __global__ void k_check_range(const int32_t *__restrict__ idx, int64_t n, int64_t limit,
                               int32_t *__restrict__ flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -63,7 +63,7 @@ __global__ void k_check_range(const int32_t *__restrict__ idx, int64_t n, int64_
 // in LDS and adds one count per run of equal indices in a lane's items.
 constexpr int kHistItems = 16;
 
-__global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ idx, int64_t n,
+static __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ idx, int64_t n,
                                               int32_t *__restrict__ cnt) {
     using Sort = hipcub::BlockRadixSort<int32_t, 256, kHistItems>;
     __shared__ typename Sort::TempStorage tmp;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ idx, i
 }
 
 // key = batch * (M + 1) + type (0 tensor, m + 1 matrix m); value = item id
-__global__ void k_order_keys(const int32_t *__restrict__ order, int64_t n, int64_t batch,
+static __global__ void k_order_keys(const int32_t *__restrict__ order, int64_t n, int64_t batch,
                              int64_t nX, int32_t M, const int64_t *__restrict__ mat_end,
                              uint32_t *__restrict__ key, int32_t *__restrict__ val) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -152,7 +152,7 @@ struct GroupArgs {
     int32_t m_J[kMaxM];
 };
 
-__global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_out,
+static __global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_out,
                                 uint64_t *__restrict__ val_out) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -189,14 +189,14 @@ __global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_out,
     }
 }
 
-__global__ void k_seg_flags(const uint64_t *__restrict__ key, int64_t n, int32_t *__restrict__ flag) {
+static __global__ void k_seg_flags(const uint64_t *__restrict__ key, int64_t n, int32_t *__restrict__ flag) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; p < n; p += stride) flag[p] = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
 }
 
 // seg_id = inclusive scan of flags - 1
-__global__ void k_seg_write(const uint64_t *__restrict__ key, const int32_t *__restrict__ flag,
+static __global__ void k_seg_write(const uint64_t *__restrict__ key, const int32_t *__restrict__ flag,
                             const int32_t *__restrict__ seg_id, int64_t n,
                             int64_t *__restrict__ seg_start, int32_t *__restrict__ seg_row,
                             uint32_t *__restrict__ seg_batch) {
@@ -1071,7 +1071,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_rows_finish(RowsArgs<T> a) {
 }
 
 // bind time: the segments with lo < length <= hi, in order, with their batch
-__global__ void k_seg_class(const int64_t *__restrict__ seg_start, int64_t nseg, int64_t lo, int64_t hi,
+static __global__ void k_seg_class(const int64_t *__restrict__ seg_start, int64_t nseg, int64_t lo, int64_t hi,
                             int32_t *__restrict__ flag) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1081,7 +1081,7 @@ __global__ void k_seg_class(const int64_t *__restrict__ seg_start, int64_t nseg,
     }
 }
 
-__global__ void k_seg_list(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t nseg,
+static __global__ void k_seg_list(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t nseg,
                            const uint32_t *__restrict__ seg_batch, const int64_t *__restrict__ seg_start,
                            int32_t *__restrict__ ids, uint32_t *__restrict__ batch, int64_t *__restrict__ c0,
                            int64_t *__restrict__ c1) {

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ U, int64_t I
 // R, Rinv, Rtot: kQrJ x kQrJ row-major.  first != 0: Rtot <- R, else
 // Rtot <- R Rtot.  A factor that is not numerically full rank sets *flag and
 // leaves R = I.
-__global__ __launch_bounds__(256) void k_chol(const double *__restrict__ part, int nb, int J, double *__restrict__ R,
+static __global__ __launch_bounds__(256) void k_chol(const double *__restrict__ part, int nb, int J, double *__restrict__ R,
                                               double *__restrict__ Rinv, double *__restrict__ Rtot, int first,
                                               int32_t *__restrict__ flag) {
     __shared__ double A[kQrJ][kQrJ];
