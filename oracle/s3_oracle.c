@@ -119,6 +119,38 @@ static int64_t rank_sum(const or_model *md)
     return s;
 }
 
+/* The positions (j_1..j_N) of every stored core value, decoded once per call
+ * instead of once per use: pos[j * N + n] = j_n of stored value j.  Only the
+ * index arithmetic moves; every sum and product below is formed in the same
+ * order as with decode() in the loop.                                      */
+typedef struct {
+    int64_t K;
+    int N;
+    int32_t *pos;
+} or_cpos;
+
+static int cpos_make(const or_model *md, or_cpos *t)
+{
+    t->K = core_size(md);
+    t->N = md->N;
+    t->pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(t->K * t->N));
+    if (!t->pos) return 0;
+    for (int64_t j = 0; j < t->K; ++j) decode(md, j, t->pos + j * t->N);
+    return 1;
+}
+
+static void cpos_free(or_cpos *t)
+{
+    free(t->pos);
+    t->pos = NULL;
+}
+
+/* the N factor rows of a tensor entry */
+static void entry_rows(const or_model *md, const int32_t *rows, const double **ur)
+{
+    for (int n = 0; n < md->N; ++n) ur[n] = urow(md, n, rows[n]);
+}
+
 /* ------------------------------------------------------------------ */
 /* Counts |Omega_X^{n,i}| (Table 2 and the rewritten objective, Eq 7)  */
 
@@ -139,27 +171,125 @@ void or_counts_build(const or_model *md, const or_tensor *X, int32_t M,
 /* ------------------------------------------------------------------ */
 /* Tucker prediction, Eq (4): x~ = sum_j g_j prod_n u^(n)_{i_n j_n}     */
 
-double or_predict_one(const or_model *md, const int32_t *rows)
+/* Order-3 and order-4 dense cores with the core positions as loop counters
+ * (stored index j = ((j_1 J_2 + j_2) J_3 + j_3) J_4 + j_4, the row-major
+ * order above): the same products, multiplied in mode order, and the same
+ * sums, added in increasing j, as the general loops over the table.       */
+static int nested(const or_model *md)
 {
-    int64_t K = core_size(md);
-    int32_t jj[OR_MAXN];
+    return !md->cp && (md->N == 3 || md->N == 4);
+}
+
+static double predict_nested(const or_model *md, const double *const *ur)
+{
+    const double *G = md->G, *a = ur[0], *b = ur[1], *c = ur[2];
+    const int J1 = md->J[0], J2 = md->J[1], J3 = md->J[2];
     double acc = 0.0;
-    for (int64_t j = 0; j < K; ++j) {
-        decode(md, j, jj);
+    int64_t j = 0;
+    if (md->N == 3) {
+        for (int j1 = 0; j1 < J1; ++j1)
+            for (int j2 = 0; j2 < J2; ++j2)
+                for (int j3 = 0; j3 < J3; ++j3, ++j) {
+                    double p = G[j];
+                    p *= a[j1]; p *= b[j2]; p *= c[j3];
+                    acc += p;
+                }
+        return acc;
+    }
+    const double *d = ur[3];
+    const int J4 = md->J[3];
+    for (int j1 = 0; j1 < J1; ++j1)
+        for (int j2 = 0; j2 < J2; ++j2)
+            for (int j3 = 0; j3 < J3; ++j3)
+                for (int j4 = 0; j4 < J4; ++j4, ++j) {
+                    double p = G[j];
+                    p *= a[j1]; p *= b[j2]; p *= c[j3]; p *= d[j4];
+                    acc += p;
+                }
+    return acc;
+}
+
+/* w_n (into w, J_1 + ... + J_N values, overwritten) and, when gG is not
+ * null, the core gradient -e prod_n u^(n) + reg_core G, in one pass        */
+static void loo_nested(const or_model *md, const double *const *ur, double *w, double e,
+                       double reg_core, double *gG)
+{
+    const double *G = md->G, *a = ur[0], *b = ur[1], *c = ur[2];
+    const int J1 = md->J[0], J2 = md->J[1], J3 = md->J[2];
+    const int J4 = md->N == 4 ? md->J[3] : 1;
+    double *w1 = w, *w2 = w1 + J1, *w3 = w2 + J2, *w4 = w3 + J3;
+    for (int k = 0; k < J1 + J2 + J3 + (md->N == 4 ? J4 : 0); ++k) w[k] = 0.0;
+    int64_t j = 0;
+    if (md->N == 3) {
+        for (int j1 = 0; j1 < J1; ++j1)
+            for (int j2 = 0; j2 < J2; ++j2)
+                for (int j3 = 0; j3 < J3; ++j3, ++j) {
+                    const double g = G[j];
+                    double p;
+                    p = g; p *= b[j2]; p *= c[j3]; w1[j1] += p;
+                    p = g; p *= a[j1]; p *= c[j3]; w2[j2] += p;
+                    p = g; p *= a[j1]; p *= b[j2]; w3[j3] += p;
+                    if (gG) {
+                        p = 1.0; p *= a[j1]; p *= b[j2]; p *= c[j3];
+                        gG[j] = -e * p + reg_core * g;
+                    }
+                }
+        return;
+    }
+    const double *d = ur[3];
+    for (int j1 = 0; j1 < J1; ++j1)
+        for (int j2 = 0; j2 < J2; ++j2)
+            for (int j3 = 0; j3 < J3; ++j3)
+                for (int j4 = 0; j4 < J4; ++j4, ++j) {
+                    const double g = G[j];
+                    double p;
+                    p = g; p *= b[j2]; p *= c[j3]; p *= d[j4]; w1[j1] += p;
+                    p = g; p *= a[j1]; p *= c[j3]; p *= d[j4]; w2[j2] += p;
+                    p = g; p *= a[j1]; p *= b[j2]; p *= d[j4]; w3[j3] += p;
+                    p = g; p *= a[j1]; p *= b[j2]; p *= c[j3]; w4[j4] += p;
+                    if (gG) {
+                        p = 1.0; p *= a[j1]; p *= b[j2]; p *= c[j3]; p *= d[j4];
+                        gG[j] = -e * p + reg_core * g;
+                    }
+                }
+}
+
+static double predict_t(const or_model *md, const or_cpos *t, const double *const *ur)
+{
+    if (nested(md)) return predict_nested(md, ur);
+    double acc = 0.0;
+    for (int64_t j = 0; j < t->K; ++j) {
+        const int32_t *jj = t->pos + j * t->N;
         double p = md->G[j];
-        for (int n = 0; n < md->N; ++n) p *= urow(md, n, rows[n])[jj[n]];
+        for (int n = 0; n < md->N; ++n) p *= ur[n][jj[n]];
         acc += p;
     }
     return acc;
 }
 
+double or_predict_one(const or_model *md, const int32_t *rows)
+{
+    or_cpos t;
+    const double *ur[OR_MAXN];
+    if (!cpos_make(md, &t)) return NAN;
+    entry_rows(md, rows, ur);
+    double acc = predict_t(md, &t, ur);
+    cpos_free(&t);
+    return acc;
+}
+
 void or_predict(const or_model *md, const or_tensor *X, double *out)
 {
+    or_cpos t;
     int32_t rows[OR_MAXN];
+    const double *ur[OR_MAXN];
+    if (!cpos_make(md, &t)) return;
     for (int64_t e = 0; e < X->nnz; ++e) {
         for (int n = 0; n < md->N; ++n) rows[n] = X->idx[n * X->nnz + e];
-        out[e] = or_predict_one(md, rows);
+        entry_rows(md, rows, ur);
+        out[e] = predict_t(md, &t, ur);
     }
+    cpos_free(&t);
 }
 
 /* ------------------------------------------------------------------ */
@@ -173,57 +303,94 @@ void or_predict(const or_model *md, const or_tensor *X, double *out)
  * prod J entries.  reg_row[n] = lambda_reg / cnt_n[i_n], reg_core =
  * lambda_reg / |Omega_X|.  Returns e.                                    */
 
-double or_tensor_item_grad(const or_model *md, const int32_t *rows, double x,
-                           const double *reg_row, double reg_core,
-                           double *gU, double *gG)
+static double item_grad_t(const or_model *md, const or_cpos *t, const double *const *ur, double x,
+                          const double *reg_row, double reg_core, double *gU, double *gG)
 {
-    int64_t K = core_size(md);
-    int32_t jj[OR_MAXN];
-    double xhat = or_predict_one(md, rows);
+    const int64_t K = t->K;
+    const int N = md->N;
+    double xhat = predict_t(md, t, ur);
     double e = x - xhat;
 
+    if (nested(md)) {
+        loo_nested(md, ur, gU, e, reg_core, gG);
+        int64_t off = 0;
+        for (int n = 0; n < N; ++n) {
+            double *w = gU + off;
+            const double *u = ur[n];
+            for (int k = 0; k < md->J[n]; ++k) w[k] = -e * w[k] + reg_row[n] * u[k];
+            off += md->J[n];
+        }
+        return e;
+    }
     int64_t off = 0;
-    for (int n = 0; n < md->N; ++n) {
+    for (int n = 0; n < N; ++n) {
         double *w = gU + off;
         for (int k = 0; k < md->J[n]; ++k) w[k] = 0.0;
         for (int64_t j = 0; j < K; ++j) {
-            decode(md, j, jj);
+            const int32_t *jj = t->pos + j * N;
             double p = md->G[j];
-            for (int m = 0; m < md->N; ++m)
-                if (m != n) p *= urow(md, m, rows[m])[jj[m]];
+            for (int m = 0; m < N; ++m)
+                if (m != n) p *= ur[m][jj[m]];
             w[jj[n]] += p;
         }
-        const double *u = urow(md, n, rows[n]);
+        const double *u = ur[n];
         for (int k = 0; k < md->J[n]; ++k) w[k] = -e * w[k] + reg_row[n] * u[k];
         off += md->J[n];
     }
     for (int64_t j = 0; j < K; ++j) {
-        decode(md, j, jj);
+        const int32_t *jj = t->pos + j * N;
         double p = 1.0;
-        for (int n = 0; n < md->N; ++n) p *= urow(md, n, rows[n])[jj[n]];
+        for (int n = 0; n < N; ++n) p *= ur[n][jj[n]];
         gG[j] = -e * p + reg_core * md->G[j];
     }
     return e;
 }
 
+double or_tensor_item_grad(const or_model *md, const int32_t *rows, double x,
+                           const double *reg_row, double reg_core,
+                           double *gU, double *gG)
+{
+    or_cpos t;
+    const double *ur[OR_MAXN];
+    if (!cpos_make(md, &t)) return NAN;
+    entry_rows(md, rows, ur);
+    double e = item_grad_t(md, &t, ur, x, reg_row, reg_core, gU, gG);
+    cpos_free(&t);
+    return e;
+}
+
 /* The leave-one-out contractions w_n = G x_{-n} {u} of one entry (Eq 3 /
  * Eq 8), straight from the definition; w receives J_1 + ... + J_N values. */
-void or_tensor_item_w(const or_model *md, const int32_t *rows, double *w)
+static void item_w_t(const or_model *md, const or_cpos *t, const double *const *ur, double *w)
 {
-    int64_t K = core_size(md);
-    int32_t jj[OR_MAXN];
+    if (nested(md)) {
+        loo_nested(md, ur, w, 0.0, 0.0, NULL);
+        return;
+    }
+    const int64_t K = t->K;
+    const int N = md->N;
     int64_t off = 0;
-    for (int n = 0; n < md->N; ++n) {
+    for (int n = 0; n < N; ++n) {
         for (int k = 0; k < md->J[n]; ++k) w[off + k] = 0.0;
         for (int64_t j = 0; j < K; ++j) {
-            decode(md, j, jj);
+            const int32_t *jj = t->pos + j * N;
             double p = md->G[j];
-            for (int m = 0; m < md->N; ++m)
-                if (m != n) p *= urow(md, m, rows[m])[jj[m]];
+            for (int m = 0; m < N; ++m)
+                if (m != n) p *= ur[m][jj[m]];
             w[off + jj[n]] += p;
         }
         off += md->J[n];
     }
+}
+
+void or_tensor_item_w(const or_model *md, const int32_t *rows, double *w)
+{
+    or_cpos t;
+    const double *ur[OR_MAXN];
+    if (!cpos_make(md, &t)) return;
+    entry_rows(md, rows, ur);
+    item_w_t(md, &t, ur, w);
+    cpos_free(&t);
 }
 
 /* ------------------------------------------------------------------ */
@@ -341,14 +508,18 @@ int64_t or_sgd_epoch(or_model *md, const or_tensor *X, int32_t M, const or_matri
     double *gu = (double *)malloc(sizeof(double) * (size_t)R);
     double *gv = (double *)malloc(sizeof(double) * (size_t)R);
     int32_t rows[OR_MAXN];
+    const double *ur[OR_MAXN];
     double reg_row[OR_MAXN];
     double reg_core = h->lambda_reg / (double)c->nX;
+    or_cpos tab;
+    if (!cpos_make(md, &tab)) { free(gU); free(gG); free(gu); free(gv); return 0; }
 
     for (int64_t t = 0; t < n_order; ++t) {
         int64_t id = order[t];
         if (id < X->nnz) {
             tensor_rows(&cx, id, rows, reg_row);
-            or_tensor_item_grad(md, rows, X->val[id], reg_row, reg_core, gU, gG);
+            entry_rows(md, rows, ur);
+            item_grad_t(md, &tab, ur, X->val[id], reg_row, reg_core, gU, gG);
             int64_t off = 0;
             for (int n = 0; n < md->N; ++n) {
                 double *u = md->U[n] + (int64_t)rows[n] * md->J[n];
@@ -371,6 +542,7 @@ int64_t or_sgd_epoch(or_model *md, const or_tensor *X, int32_t M, const or_matri
             }
         }
     }
+    cpos_free(&tab);
     free(gU); free(gG); free(gu); free(gv);
     return n_order;
 }
@@ -425,8 +597,11 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
     double LG = 0.0;
     double kappa = (double)(N + 1);
     int32_t rows[OR_MAXN];
+    const double *ur[OR_MAXN];
     double reg_row[OR_MAXN];
     double reg_core = h->lambda_reg / (double)c->nX;
+    or_cpos tab;
+    if (!cpos_make(md, &tab)) return -1;
 
     int64_t nb_total = (n_order + batch - 1) / batch;
     int64_t last = n_batches < 0 ? nb_total : first_batch + n_batches;
@@ -440,7 +615,8 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
             int64_t id = order[t];
             if (id < X->nnz) {
                 tensor_rows(&cx, id, rows, reg_row);
-                or_tensor_item_grad(md, rows, X->val[id], reg_row, reg_core, gU, gG);
+                entry_rows(md, rows, ur);
+                item_grad_t(md, &tab, ur, X->val[id], reg_row, reg_core, gU, gG);
                 int64_t off = 0;
                 for (int n = 0; n < N; ++n) {
                     double *a = aU[n] + (int64_t)rows[n] * md->J[n];
@@ -449,7 +625,7 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
                 }
                 for (int64_t j = 0; j < K; ++j) aG[j] += gG[j];
                 if (damping) {
-                    or_tensor_item_w(md, rows, w);
+                    item_w_t(md, &tab, ur, w);
                     double pu = 1.0;
                     off = 0;
                     for (int n = 0; n < N; ++n) {
@@ -532,6 +708,7 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
     }
     for (int n = 0; n < N; ++n) { free(aU[n]); free(LU[n]); }
     for (int m = 0; m < M; ++m) { free(aV[m]); free(LV[m]); }
+    cpos_free(&tab);
     free(aG); free(gU); free(gG); free(gu); free(gv); free(w);
     return done;
 }
@@ -547,12 +724,17 @@ void or_loss(const or_model *md, const or_tensor *X, int32_t M, const or_matrix 
              const or_counts *c, const or_hyper *h, double *out)
 {
     int32_t rows[OR_MAXN];
+    const double *ur[OR_MAXN];
     double sse = 0.0;
+    or_cpos tab;
+    if (!cpos_make(md, &tab)) { out[0] = out[1] = out[2] = NAN; return; }
     for (int64_t e = 0; e < X->nnz; ++e) {
         for (int n = 0; n < md->N; ++n) rows[n] = X->idx[n * X->nnz + e];
-        double r = X->val[e] - or_predict_one(md, rows);
+        entry_rows(md, rows, ur);
+        double r = X->val[e] - predict_t(md, &tab, ur);
         sse += r * r;
     }
+    cpos_free(&tab);
     double reg = 0.0;
     int64_t K = core_size(md);
     for (int64_t j = 0; j < K; ++j) reg += md->G[j] * md->G[j];
@@ -595,12 +777,17 @@ double or_rmse(const or_model *md, const or_tensor *T)
 {
     if (T->nnz == 0) return 0.0;
     int32_t rows[OR_MAXN];
+    const double *ur[OR_MAXN];
     double s = 0.0;
+    or_cpos tab;
+    if (!cpos_make(md, &tab)) return NAN;
     for (int64_t e = 0; e < T->nnz; ++e) {
         for (int n = 0; n < md->N; ++n) rows[n] = T->idx[n * T->nnz + e];
-        double r = T->val[e] - or_predict_one(md, rows);
+        entry_rows(md, rows, ur);
+        double r = T->val[e] - predict_t(md, &tab, ur);
         s += r * r;
     }
+    cpos_free(&tab);
     return sqrt(s / (double)T->nnz);
 }
 
@@ -626,11 +813,15 @@ void or_full_grad(const or_model *md, const or_tensor *X, int32_t M, const or_ma
     double *gu = (double *)malloc(sizeof(double) * (size_t)R);
     double *gv = (double *)malloc(sizeof(double) * (size_t)R);
     int32_t rows[OR_MAXN];
+    const double *ur[OR_MAXN];
     double reg_row[OR_MAXN];
     double reg_core = h->lambda_reg / (double)c->nX;
+    or_cpos tab;
+    if (!cpos_make(md, &tab)) { free(gU); free(gG); free(gu); free(gv); return; }
     for (int64_t e = 0; e < X->nnz; ++e) {
         tensor_rows(&cx, e, rows, reg_row);
-        or_tensor_item_grad(md, rows, X->val[e], reg_row, reg_core, gU, gG);
+        entry_rows(md, rows, ur);
+        item_grad_t(md, &tab, ur, X->val[e], reg_row, reg_core, gU, gG);
         int64_t off = 0;
         for (int n = 0; n < N; ++n) {
             double *a = dU[n] + (int64_t)rows[n] * md->J[n];
@@ -652,6 +843,7 @@ void or_full_grad(const or_model *md, const or_tensor *X, int32_t M, const or_ma
             for (int k = 0; k < J; ++k) { au[k] += gu[k]; av[k] += gv[k]; }
         }
     }
+    cpos_free(&tab);
     free(gU); free(gG); free(gu); free(gv);
 }
 
