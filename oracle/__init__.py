@@ -14,6 +14,8 @@ Every function here cites the part of the paper it follows:
 * ``matrix_item_grad``    -- coupled-matrix entry, Eq (8) / Algorithm 1
 * ``sgd_epoch``           -- Algorithm 1 with one worker
 * ``minibatch_epoch``     -- the library's deterministic batched reading of it
+                             (optionally evaluated by several threads, summed
+                             in the same order: bitwise the same result)
 * ``loss``                -- Eq (7), per-entry form
 * ``rmse``                -- held-out RMSE, Section 4.1
 * ``full_grad``           -- sum of per-entry gradients (= gradient of Eq 7)

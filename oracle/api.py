@@ -54,7 +54,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-pthread",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -85,6 +85,10 @@ def _L():
         lib.or_sgd_epoch.restype = C.c_int64
         lib.or_minibatch_epoch.argtypes = [M, T, C.c_int32, Y, Cn, H, _i64p, C.c_int64,
                                            C.c_int64, C.c_double, C.c_int64, C.c_int64, C.c_int32]
+        lib.or_minibatch_epoch_mt.argtypes = [M, T, C.c_int32, Y, Cn, H, _i64p, C.c_int64,
+                                              C.c_int64, C.c_double, C.c_int64, C.c_int64, C.c_int32,
+                                              C.c_int32]
+        lib.or_minibatch_epoch_mt.restype = C.c_int64
         lib.or_tensor_item_w.argtypes = [M, _i32p, _dp]
         lib.or_minibatch_epoch.restype = C.c_int64
         lib.or_loss.argtypes = [M, T, C.c_int32, Y, Cn, H, _dp]
@@ -290,15 +294,20 @@ def sgd_epoch(params: Params, problem, order, eta: float, lambda_reg=None, lambd
 
 
 def minibatch_epoch(params: Params, problem, order, batch: int, eta: float, first_batch: int = 0,
-                    n_batches: int = -1, lambda_reg=None, lambda_m=None, damping: bool = False) -> int:
+                    n_batches: int = -1, lambda_reg=None, lambda_m=None, damping: bool = False,
+                    threads: int = 1) -> int:
     """Deterministic mini-batch pass (batch-start gradients summed, then applied,
-    optionally with the curvature damping of each block's step). In place."""
+    optionally with the curvature damping of each block's step). In place.
+    threads > 1: the items' gradients are evaluated by that many threads and
+    summed in the same order (bitwise the same result)."""
     lr, lm = _hyper(problem, lambda_reg, lambda_m)
     r = _Run(params, problem, lr, lm)
     order = np.ascontiguousarray(order, dtype=np.int64)
-    return int(_L().or_minibatch_epoch(C.byref(r.md), C.byref(r.d.X), r.d.M, r.d.Y, C.byref(r.ch.c),
-                                       C.byref(r.h), _ptr(order, _i64p), order.shape[0], int(batch),
-                                       float(eta), int(first_batch), int(n_batches), int(bool(damping))))
+    args = (C.byref(r.md), C.byref(r.d.X), r.d.M, r.d.Y, C.byref(r.ch.c), C.byref(r.h), _ptr(order, _i64p),
+            order.shape[0], int(batch), float(eta), int(first_batch), int(n_batches), int(bool(damping)))
+    if threads > 1:
+        return int(_L().or_minibatch_epoch_mt(*args, int(threads)))
+    return int(_L().or_minibatch_epoch(*args))
 
 
 def loss(params: Params, problem, lambda_reg=None, lambda_m=None):

@@ -32,6 +32,7 @@
  *   - the core is updated after every tensor entry (one worker, P = 1).
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -710,6 +711,270 @@ int64_t or_minibatch_epoch(or_model *md, const or_tensor *X, int32_t M, const or
     for (int m = 0; m < M; ++m) { free(aV[m]); free(LV[m]); }
     cpos_free(&tab);
     free(aG); free(gU); free(gG); free(gu); free(gv); free(w);
+    return done;
+}
+
+/* ------------------------------------------------------------------ */
+/* The same deterministic mini-batch epoch with `threads` worker threads,
+ * giving bitwise the results of or_minibatch_epoch.  Per batch, in blocks
+ * of at most OR_MT_BLOCK items:
+ *   1. the threads take contiguous ranges of items and evaluate each item's
+ *      error, row gradients and curvature terms at the batch-start values
+ *      (the same expressions as above), into per-item slots;
+ *   2. one thread adds the slots to the row accumulators in item order;
+ *   3. the threads take ranges of core values j and add, item by item in
+ *      order, the item's core-gradient term -e prod_n u^(n) + reg G_j.
+ * Every accumulator therefore sums the same terms in the same order as the
+ * sequential loop; only the evaluation is spread over threads.  The apply
+ * step is the sequential one.                                            */
+
+#define OR_MT_BLOCK 16384
+
+typedef struct {
+    const or_ctx *cx;
+    const or_cpos *tab;
+    const int64_t *order;
+    int64_t t0, n;            /* block: items order[t0 .. t0 + n) */
+    int32_t damping;
+    double reg_core;
+    int64_t R;                /* sum of ranks: slot width */
+    double *e;                /* [n]      tensor error; unused for matrices */
+    double *g;                /* [n][2R]  row gradients (tensor: J_1..J_N;
+                                            matrix: g_u then g_v)          */
+    double *cu;               /* [n][N]   curvature terms per row        */
+    double *cg;               /* [n]      core curvature term            */
+    int32_t *rows;            /* [n][N]   tensor rows                    */
+    /* phase 3 */
+    double *aG;
+    int64_t j0, j1;
+    int64_t lo, hi;           /* phase 1: item range of this thread */
+} or_mt_job;
+
+static void mt_eval(or_mt_job *jb)
+{
+    const or_ctx *cx = jb->cx;
+    const or_model *md = cx->md;
+    const int N = md->N;
+    const int64_t R = jb->R;
+    double *w = (double *)malloc(sizeof(double) * (size_t)R);
+    double *gG = (double *)malloc(sizeof(double) * (size_t)jb->tab->K);
+    double reg_row[OR_MAXN];
+    const double *ur[OR_MAXN];
+    for (int64_t i = jb->lo; i < jb->hi; ++i) {
+        int64_t id = jb->order[jb->t0 + i];
+        double *g = jb->g + i * 2 * R;
+        if (id < cx->X->nnz) {
+            int32_t *rows = jb->rows + i * N;
+            tensor_rows(cx, id, rows, reg_row);
+            entry_rows(md, rows, ur);
+            jb->e[i] = item_grad_t(md, jb->tab, ur, cx->X->val[id], reg_row, jb->reg_core, g, gG);
+            if (jb->damping) {
+                item_w_t(md, jb->tab, ur, w);
+                double pu = 1.0;
+                int64_t off = 0;
+                for (int n = 0; n < N; ++n) {
+                    const double *u = ur[n];
+                    double ww = 0.0, uu = 0.0;
+                    for (int k = 0; k < md->J[n]; ++k) { ww += w[off + k] * w[off + k]; uu += u[k] * u[k]; }
+                    jb->cu[i * N + n] = ww + reg_row[n];
+                    pu *= uu;
+                    off += md->J[n];
+                }
+                if (md->cp) {
+                    pu = 0.0;
+                    for (int r = 0; r < md->J[0]; ++r) {
+                        double q = 1.0;
+                        for (int n = 0; n < N; ++n) {
+                            double v = ur[n][r];
+                            q *= v * v;
+                        }
+                        pu += q;
+                    }
+                }
+                jb->cg[i] = pu + jb->reg_core;
+            }
+        } else {
+            int64_t e;
+            int m = item_matrix(cx, id, &e);
+            int cm = md->mode[m];
+            int32_t J = md->J[cm];
+            const double *u = md->U[cm] + (int64_t)cx->Y[m].row[e] * J;
+            const double *v = md->V[m] + (int64_t)cx->Y[m].col[e] * J;
+            double reg_v = cx->h->lambda_reg / (double)cx->c->cntV[m][cx->Y[m].col[e]];
+            or_matrix_item_grad(u, v, J, cx->Y[m].val[e], cx->h->lambda_m, reg_v, g, g + J);
+            if (jb->damping) {
+                double uu = 0.0, vv = 0.0;
+                for (int k = 0; k < J; ++k) { uu += u[k] * u[k]; vv += v[k] * v[k]; }
+                jb->cu[i * N + 0] = cx->h->lambda_m * vv;
+                jb->cu[i * N + 1] = cx->h->lambda_m * uu + cx->h->lambda_m * reg_v;
+            }
+        }
+    }
+    free(w);
+    free(gG);
+}
+
+static void *mt_eval_thread(void *arg)
+{
+    mt_eval((or_mt_job *)arg);
+    return NULL;
+}
+
+/* core-gradient terms of the block's tensor items, core values [j0, j1) */
+static void *mt_core_thread(void *arg)
+{
+    or_mt_job *jb = (or_mt_job *)arg;
+    const or_ctx *cx = jb->cx;
+    const or_model *md = cx->md;
+    const int N = md->N;
+    const double *ur[OR_MAXN];
+    for (int64_t i = 0; i < jb->n; ++i) {
+        int64_t id = jb->order[jb->t0 + i];
+        if (id >= cx->X->nnz) continue;
+        entry_rows(md, jb->rows + i * N, ur);
+        const double e = jb->e[i];
+        for (int64_t j = jb->j0; j < jb->j1; ++j) {
+            const int32_t *jj = jb->tab->pos + j * N;
+            double p = 1.0;
+            for (int n = 0; n < N; ++n) p *= ur[n][jj[n]];
+            jb->aG[j] += -e * p + jb->reg_core * md->G[j];
+        }
+    }
+    return NULL;
+}
+
+static void mt_run(void *(*fn)(void *), or_mt_job *jobs, int threads)
+{
+    pthread_t th[64];
+    for (int k = 1; k < threads; ++k) pthread_create(&th[k], NULL, fn, &jobs[k]);
+    fn(&jobs[0]);
+    for (int k = 1; k < threads; ++k) pthread_join(th[k], NULL);
+}
+
+int64_t or_minibatch_epoch_mt(or_model *md, const or_tensor *X, int32_t M, const or_matrix *Y,
+                              const or_counts *c, const or_hyper *h, const int64_t *order,
+                              int64_t n_order, int64_t batch, double eta,
+                              int64_t first_batch, int64_t n_batches, int32_t damping,
+                              int32_t threads)
+{
+    if (threads < 1) threads = 1;
+    if (threads > 64) threads = 64;
+    or_ctx cx;
+    ctx_init(&cx, md, X, M, Y, c, h);
+    const int N = md->N;
+    const int64_t K = core_size(md);
+    const int64_t R = rank_sum(md);
+    or_cpos tab;
+    if (!cpos_make(md, &tab)) return -1;
+    double *aU[OR_MAXN], *aV[OR_MAXM], *LU[OR_MAXN], *LV[OR_MAXM];
+    for (int n = 0; n < N; ++n) aU[n] = (double *)calloc((size_t)(md->dims[n] * md->J[n]), sizeof(double));
+    for (int m = 0; m < M; ++m) aV[m] = (double *)calloc((size_t)(md->cols[m] * md->J[md->mode[m]]), sizeof(double));
+    for (int n = 0; n < N; ++n) LU[n] = (double *)calloc((size_t)md->dims[n], sizeof(double));
+    for (int m = 0; m < M; ++m) LV[m] = (double *)calloc((size_t)md->cols[m], sizeof(double));
+    double *aG = (double *)calloc((size_t)K, sizeof(double));
+    double LG = 0.0;
+    const double kappa = (double)(N + 1);
+    const double reg_core = h->lambda_reg / (double)c->nX;
+    const int64_t S = OR_MT_BLOCK;
+    double *be = (double *)malloc(sizeof(double) * (size_t)S);
+    double *bg = (double *)malloc(sizeof(double) * (size_t)(S * 2 * R));
+    double *bcu = (double *)malloc(sizeof(double) * (size_t)(S * N));
+    double *bcg = (double *)malloc(sizeof(double) * (size_t)S);
+    int32_t *brows = (int32_t *)malloc(sizeof(int32_t) * (size_t)(S * N));
+    or_mt_job jobs[64];
+
+    int64_t nb_total = (n_order + batch - 1) / batch;
+    int64_t last = n_batches < 0 ? nb_total : first_batch + n_batches;
+    if (last > nb_total) last = nb_total;
+    int64_t done = 0;
+    for (int64_t b = first_batch; b < last; ++b) {
+        int64_t t0 = b * batch, t1 = t0 + batch;
+        if (t1 > n_order) t1 = n_order;
+        for (int64_t s0 = t0; s0 < t1; s0 += S) {
+            const int64_t n = (t1 - s0 < S) ? t1 - s0 : S;
+            for (int k = 0; k < threads; ++k) {
+                or_mt_job *jb = &jobs[k];
+                jb->cx = &cx; jb->tab = &tab; jb->order = order; jb->t0 = s0; jb->n = n;
+                jb->damping = damping; jb->reg_core = reg_core; jb->R = R;
+                jb->e = be; jb->g = bg; jb->cu = bcu; jb->cg = bcg; jb->rows = brows; jb->aG = aG;
+                jb->lo = n * k / threads; jb->hi = n * (k + 1) / threads;
+                jb->j0 = K * k / threads; jb->j1 = K * (k + 1) / threads;
+            }
+            /* 1: evaluation */
+            mt_run(mt_eval_thread, jobs, threads);
+            /* 2: row sums in item order */
+            for (int64_t i = 0; i < n; ++i) {
+                int64_t id = order[s0 + i];
+                const double *g = bg + i * 2 * R;
+                if (id < X->nnz) {
+                    const int32_t *rows = brows + i * N;
+                    int64_t off = 0;
+                    for (int q = 0; q < N; ++q) {
+                        double *a = aU[q] + (int64_t)rows[q] * md->J[q];
+                        for (int k = 0; k < md->J[q]; ++k) a[k] += g[off + k];
+                        off += md->J[q];
+                    }
+                    if (damping) {
+                        for (int q = 0; q < N; ++q) LU[q][rows[q]] += bcu[i * N + q];
+                        LG += bcg[i];
+                    }
+                } else {
+                    int64_t e;
+                    int m = item_matrix(&cx, id, &e);
+                    int cm = md->mode[m];
+                    int32_t J = md->J[cm];
+                    double *au = aU[cm] + (int64_t)Y[m].row[e] * J;
+                    double *av = aV[m] + (int64_t)Y[m].col[e] * J;
+                    for (int k = 0; k < J; ++k) { au[k] += g[k]; av[k] += g[J + k]; }
+                    if (damping) {
+                        LU[cm][Y[m].row[e]] += bcu[i * N + 0];
+                        LV[m][Y[m].col[e]] += bcu[i * N + 1];
+                    }
+                }
+            }
+            /* 3: core-gradient sums, by ranges of core values */
+            mt_run(mt_core_thread, jobs, threads);
+        }
+        /* apply and clear the touched accumulators (as in the sequential epoch) */
+        for (int64_t t = t0; t < t1; ++t) {
+            int64_t id = order[t];
+            if (id < X->nnz) {
+                for (int n = 0; n < N; ++n) {
+                    int64_t i = X->idx[n * X->nnz + id];
+                    double *u = md->U[n] + i * md->J[n];
+                    double *a = aU[n] + i * md->J[n];
+                    double st = damped(eta, kappa, LU[n][i], damping);
+                    for (int k = 0; k < md->J[n]; ++k) { u[k] -= st * a[k]; a[k] = 0.0; }
+                    LU[n][i] = 0.0;
+                }
+            } else {
+                int64_t e;
+                int m = item_matrix(&cx, id, &e);
+                int cm = md->mode[m];
+                int32_t J = md->J[cm];
+                double *u = md->U[cm] + (int64_t)Y[m].row[e] * J;
+                double *au = aU[cm] + (int64_t)Y[m].row[e] * J;
+                double *v = md->V[m] + (int64_t)Y[m].col[e] * J;
+                double *av = aV[m] + (int64_t)Y[m].col[e] * J;
+                double su = damped(eta, kappa, LU[cm][Y[m].row[e]], damping);
+                double sv = damped(eta, kappa, LV[m][Y[m].col[e]], damping);
+                for (int k = 0; k < J; ++k) {
+                    u[k] -= su * au[k]; au[k] = 0.0;
+                    v[k] -= sv * av[k]; av[k] = 0.0;
+                }
+                LU[cm][Y[m].row[e]] = 0.0;
+                LV[m][Y[m].col[e]] = 0.0;
+            }
+        }
+        double sg = damped(eta, kappa, LG, damping);
+        for (int64_t j = 0; j < K; ++j) { md->G[j] -= sg * aG[j]; aG[j] = 0.0; }
+        LG = 0.0;
+        ++done;
+    }
+    for (int n = 0; n < N; ++n) { free(aU[n]); free(LU[n]); }
+    for (int m = 0; m < M; ++m) { free(aV[m]); free(LV[m]); }
+    free(aG); free(be); free(bg); free(bcu); free(bcg); free(brows);
+    cpos_free(&tab);
     return done;
 }
 

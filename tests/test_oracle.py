@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from synth import get_config, make_problem, init_params, item_order
-from tests.dense_ref import dense_predict, dense_tucker, fd_grad, item_phi, rel
+from tests.dense_ref import damped_batch_step, dense_predict, dense_tucker, fd_grad, item_phi, rel
 
 
 def _problem(name, **kw):
@@ -488,3 +488,77 @@ def test_cp_qr_is_rejected():
     rng = np.random.default_rng(43)
     with pytest.raises(ValueError):
         oracle.qr_orthogonalize(_cp_params(rng, (5, 4, 3), 2, []))
+
+
+# ------------------------------------- batched epochs against a restatement
+# The damped mini-batch rule (several entries per row, matrix rows on both
+# sides, the per-batch reset of sums and curvatures, the hyper-diagonal
+# core) against tests/dense_ref.damped_batch_step, which restates Eq (8) and
+# the damping reading with np.einsum and per-block dictionaries.
+
+def _cp_of(params, J):
+    U = [u[:, :J].copy() for u in params.U]
+    V = [v[:, :J].copy() for v in params.V]
+    g = np.linspace(0.4, -0.3, J)
+    return oracle.Params.from_arrays(U, g, V, params.modes, cp=True)
+
+
+@pytest.mark.parametrize("name,eta,batch,cp,damping", [
+    ("tiny3", 5.0, 13, False, True),
+    ("tiny4", 5.0, 9, False, True),
+    ("cfg1", 2.0, 700, False, True),
+    ("tiny3", 5.0, 13, True, True),
+    ("tiny4", 5.0, 9, True, True),
+    ("tiny3", 0.02, 13, False, False),
+    ("cfg1", 0.002, 700, False, False),
+])
+def test_batched_epoch_matches_independent_restatement(name, eta, batch, cp, damping):
+    cfg, p, params = _problem(name)
+    if cp:
+        params = _cp_of(params, min(cfg.ranks))
+    cnt, cntV = oracle.counts(params, p)
+    order = item_order(p.n_items, 5, 0)
+    got = params.copy()
+    oracle.minibatch_epoch(got, p, order, batch, eta, 0, 3, damping=damping)
+    U, G, V = params.U, params.G, params.V
+    mats = [(p.mat_row[m], p.mat_col[m], p.mat_val[m]) for m in range(len(p.mat_val))]
+    damped = 0
+    for b in range(3):
+        items = order[b * batch:(b + 1) * batch]
+        U, G, V, nd = damped_batch_step(U, G, V, params.modes, items, (p.train_idx, p.train_val), mats, eta,
+                                        cfg.lambda_reg, cfg.lambda_m, cnt, cntV, p.n_train, damping=damping,
+                                        cp=cp)
+        damped += nd
+    if damping:
+        assert damped > 0  # the rule is exercised, not just plain SGD sums
+    for a, b_ in zip(got.U + [got.G] + got.V, U + [G] + V):
+        assert rel(a, b_) < 1e-13
+        assert np.max(np.abs(a - b_)) <= 1e-13 * max(1.0, np.max(np.abs(b_)))
+
+
+def test_threaded_batched_epoch_is_bitwise_sequential():
+    for name, cp in [("tiny3", False), ("tiny4", False), ("cfg1", False), ("cfg5_slice", False), ("tiny4", True)]:
+        cfg, p, params = _problem(name)
+        if cp:
+            params = _cp_of(params, 1)
+        order = item_order(p.n_items, 3, 0)[:3000]
+        for damping, eta in [(True, 0.5), (False, 0.01)]:
+            for batch in (1, 7, 500, 10 ** 9):
+                ref = params.copy()
+                oracle.minibatch_epoch(ref, p, order, batch, eta, damping=damping)
+                for threads in (2, 5):
+                    got = params.copy()
+                    oracle.minibatch_epoch(got, p, order, batch, eta, damping=damping, threads=threads)
+                    for a, b in zip(got.U + [got.G] + got.V, ref.U + [ref.G] + ref.V):
+                        assert np.array_equal(a, b)
+
+
+def test_matrix_predict_is_row_dot_products():
+    rng = np.random.default_rng(21)
+    for J in (1, 3, 10, 16):
+        params = _rand_params(rng, (30, 4, 5), (J, 2, 2), [(0, 25)])
+        row = rng.integers(0, 30, size=200)
+        col = rng.integers(0, 25, size=200)
+        want = np.einsum("ij,ij->i", params.U[0][row], params.V[0][col])
+        got = oracle.matrix_predict(params, 0, row, col)
+        assert rel(got, want) < 1e-15
