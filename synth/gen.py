@@ -39,6 +39,8 @@ from __future__ import annotations
 
 import dataclasses
 import functools
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
@@ -127,7 +129,6 @@ def _rng(seed: int, stream: int, sub: int = 0) -> np.random.Generator:
 
 
 @functools.lru_cache(maxsize=16)
-@functools.lru_cache(maxsize=8)
 def _zipf_cdf(I: int, s: float) -> np.ndarray:
     w = np.arange(1, I + 1, dtype=np.float64) ** (-float(s))
     cdf = np.cumsum(w)
@@ -136,14 +137,32 @@ def _zipf_cdf(I: int, s: float) -> np.ndarray:
     return cdf
 
 
+# worker threads for the large array steps (numpy's searches and sorts run
+# without the interpreter lock); results do not depend on the thread count
+_THREADS = max(1, min(16, os.cpu_count() or 1))
+_pool = None
+
+
+def _map(fn, items):
+    global _pool
+    if _pool is None:
+        _pool = ThreadPoolExecutor(_THREADS)
+    return list(_pool.map(fn, items))
+
+
 def zipf_ranks(rng: np.random.Generator, I: int, s: float, n: int) -> np.ndarray:
     """Draw n ranks in [0, I) with P(r) proportional to (r+1)^-s (bounded Zipf)."""
     cdf = _zipf_cdf(int(I), float(s))
     u = rng.random(n)
-    # inverse CDF; the uniforms are looked up in sorted order (cache-friendly)
-    order = np.argsort(u)
+    # inverse CDF, looked up in chunks by the worker threads
+    chunks = np.array_split(np.arange(n), max(1, min(4 * _THREADS, n // 65536 + 1)))
     r = np.empty(n, dtype=np.int64)
-    r[order] = np.searchsorted(cdf, u[order], side="right")
+
+    def look(ix):
+        if ix.size:
+            r[ix[0]:ix[-1] + 1] = np.searchsorted(cdf, u[ix[0]:ix[-1] + 1], side="right")
+
+    _map(look, chunks)
     return np.minimum(r, I - 1)
 
 
@@ -173,6 +192,48 @@ def _draw_values(rng, law, n):
 _progress = None
 
 
+def _bucket_of(keys: np.ndarray, nbucket: int) -> np.ndarray:
+    """A hash bucket per key (Fibonacci hashing of the 64-bit key)."""
+    if nbucket == 1:
+        return np.zeros(keys.size, dtype=np.uint8)
+    return ((keys.view(np.uint64) * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(56)).astype(np.uint8)
+
+
+def _fresh_positions(keys: np.ndarray, runs: List[List[np.ndarray]]) -> np.ndarray:
+    """Positions of the keys of one draw that occur there for the first time
+    and are not in the kept set (runs: per hash bucket, 1 or 256 of them,
+    sorted runs of kept keys), which they join; increasing positions."""
+    nbucket = len(runs)
+    b = _bucket_of(keys, nbucket)
+    perm = np.argsort(b, kind="stable")  # draw order kept within a bucket
+    bounds = np.concatenate([[0], np.cumsum(np.bincount(b, minlength=nbucket))])
+
+    def work(j):
+        idx = perm[bounds[j]:bounds[j + 1]]
+        if idx.size == 0:
+            return idx
+        sub = keys[idx]
+        o = np.argsort(sub, kind="stable")
+        srt = sub[o]
+        first = np.ones(srt.size, dtype=bool)
+        first[1:] = srt[1:] != srt[:-1]
+        cand, pos = srt[first], idx[o[first]]
+        seen = np.zeros(cand.size, dtype=bool)
+        for r in runs[j]:
+            at = np.minimum(np.searchsorted(r, cand), r.size - 1)
+            seen |= r[at] == cand
+        keep = ~seen
+        if keep.any():
+            runs[j].append(cand[keep])
+            if len(runs[j]) > 8:  # fold the small runs into one
+                runs[j][:] = [runs[j][0], np.sort(np.concatenate(runs[j][1:]))]
+        return pos[keep]
+
+    pos = np.concatenate(_map(work, range(nbucket)) if nbucket > 1 else [work(0)])
+    pos.sort()
+    return pos
+
+
 def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) -> np.ndarray:
     """Draw n distinct coordinate tuples; draw(k) returns int64 [len(dims), k].
 
@@ -185,35 +246,17 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) 
     total = int(strides[0]) * int(dims[0])
     if n > total:
         raise ValueError(f"{n} distinct entries requested from a space of {total}")
-    # keys kept so far, as a few sorted runs: a round costs O(its own size x
-    # runs x log n) instead of a re-sort of everything kept
-    runs: List[np.ndarray] = []
+    # hash buckets (searched by the worker threads) for large sets
+    runs: List[List[np.ndarray]] = [[] for _ in range(256 if n >= (1 << 20) else 1)]
     n_kept = 0
     kept = []
     need = n
     for _ in range(max_rounds):
         c = draw(need)
         keys = (c * strides[:, None]).sum(axis=0)
-        # first occurrence within this draw
-        _, first = np.unique(keys, return_index=True)
-        first.sort()
-        c, keys = c[:, first], keys[first]
-        if runs:
-            q = np.argsort(keys)
-            ks = keys[q]
-            seen = np.zeros(keys.size, dtype=bool)
-            for r in runs:
-                pos = np.minimum(np.searchsorted(r, ks), r.size - 1)
-                seen |= r[pos] == ks
-            fresh = np.empty(keys.size, dtype=bool)
-            fresh[q] = ~seen
-            c, keys = c[:, fresh], keys[fresh]
-        kept.append(c)
-        n_kept += keys.size
-        if keys.size:
-            runs.append(np.sort(keys))
-        if len(runs) > 8:  # fold the small runs into one
-            runs = [runs[0], np.sort(np.concatenate(runs[1:]))]
+        pos = _fresh_positions(keys, runs)
+        kept.append(c[:, pos])
+        n_kept += pos.size
         need = n - n_kept
         if _progress:
             _progress(f"{n_kept:,} of {n:,} distinct coordinates")
@@ -288,8 +331,10 @@ def _make_problem(cfg: Config) -> Problem:
     n = cfg.nnz
     n_test = int(round(cfg.test_frac * n))
     sp = _rng(cfg.seed_split, _S_SPLIT).permutation(n)
-    test_sel = np.sort(sp[:n_test])
-    train_sel = np.sort(sp[n_test:])
+    is_test = np.zeros(n, dtype=bool)
+    is_test[sp[:n_test]] = True
+    test_sel = np.flatnonzero(is_test)   # increasing, as a sort of sp[:n_test]
+    train_sel = np.flatnonzero(~is_test)
     p = Problem(
         cfg=cfg,
         train_idx=np.ascontiguousarray(coords[:, train_sel].astype(np.int32)),
