@@ -219,6 +219,19 @@ s3_status s3_rmse(s3_plan *plan, double *out, void *stream);
 s3_status s3_predict(s3_plan *plan, const int32_t *idx, int64_t nnz, void *xhat,
                      void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as s3_predict, bitwise, with its working memory (the index-check
+ * flag and the zero-padded core, at most 64 KiB) taken from a static array
+ * in the library's device code instead of the plan's workspace.  Allocates
+ * nothing.  Each GPU holds one copy of that array until the process ends;
+ * it is set up by s3_bind on that device.  Calls that overlap on one GPU (on
+ * different streams, or from different plans) share it and race: serialise
+ * them.  S3_ERR_WORKSPACE if the plan's padded core does not fit.
+ * Synchronises `stream` (index check), like s3_predict.                   */
+s3_status s3_predict_noalloc(s3_plan *plan, const int32_t *idx, int64_t nnz, void *xhat,
+                             void *stream);
+
 /* Forward of coupled matrix m: yhat[e] = u^(c_m)_{row[e]} . v_{col[e]} for nnz
  * entries (row, col, yhat on the device; yhat in the compute type).
  * Asynchronous.                                                           */

@@ -61,7 +61,7 @@ struct KernelSet {
                         hipStream_t, hipEvent_t, hipEvent_t);
     void (*core_partial)(s3_plan *, const int32_t *, int64_t, hipStream_t);
     void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
-    void (*predict)(s3_plan *, const int32_t *, int64_t, void *, hipStream_t);
+    void (*predict)(s3_plan *, const int32_t *, int64_t, void *, const void *, hipStream_t);  // Gp: padded core
     void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t, hipEvent_t, hipEvent_t);
     int det_chunk;  // tensor entries per det block and core chunk
 };
@@ -180,10 +180,10 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
         hipLaunchKernelGGL((k_sq_err_tensor<N, JP, T, CT>), dim3(sq_blocks(nnz)), dim3(256), 0, st, a,
                            (const T *)p->Gp, part);
     }
-    static void predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *out, hipStream_t st) {
+    static void predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *out, const void *Gp, hipStream_t st) {
         auto a = tensor_args<T>(p, idx, nullptr, nnz);
         hipLaunchKernelGGL((k_predict<N, JP, T, CT>), dim3(grid_for(nnz, 256, 1ll << 30)), dim3(256), 0, st, a,
-                           (const T *)p->Gp, (T *)out);
+                           (const T *)Gp, (T *)out);
     }
     static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st, hipEvent_t e0,
                           hipEvent_t e1) {

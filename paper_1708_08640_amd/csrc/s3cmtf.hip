@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -155,12 +156,12 @@ template <typename T> CoreStep<T> core_step(s3_plan *p, int64_t nt, double eta, 
     return c;
 }
 
-template <typename T> void pad_core(s3_plan *p, hipStream_t st) {
+template <typename T> void pad_core(s3_plan *p, hipStream_t st, void *dst = nullptr) {
     const int *J = p->d.rank;
     // a hyper-diagonal core pads as a one-mode core of J values
     const int Nc = p->d.core_kind == S3_CORE_CP ? 1 : p->N;
     hipLaunchKernelGGL(k_pad_core<T>, dim3(grid_for(p->KP, 256, 64)), dim3(256), 0, st, (const T *)p->b.G,
-                       (T *)p->Gp, Nc, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1);
+                       (T *)(dst ? dst : p->Gp), Nc, p->JP, J[0], J[1], J[2], p->N > 3 ? J[3] : 1);
 }
 
 template <typename T> void fill(void *ptr, int64_t n, double v, hipStream_t st) {
@@ -234,6 +235,40 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
 
 template <typename T> size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz,
                                     const int64_t *y_nnz, bool with_order, size_t *temp_bytes_out);
+
+}  // namespace
+
+// ------------------------------------------------ allocation-free prediction
+
+// Device memory of s3_predict_noalloc: one flag word for the index check (in
+// the first 256 bytes), then the zero-padded core.  Each GPU the library runs
+// on holds its own copy until the process ends.
+constexpr size_t kStaticScratchBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};  // per device: the address of its copy
+
+// Address of `scratch` on the current device, looked up once per device with
+// that device current.  (The array's name in host code is only a host-side
+// handle; kernels must be given this address.)
+s3_status scratch_ptr(s3_plan *p, void **out) {
+    int dev = 0;
+    HIPCHK(p, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(p, S3_ERR_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(p, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(p, S3_ERR_HIP, "hipGetSymbolAddress gave a null address");
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return S3_OK;
+}
 
 }  // namespace
 
@@ -626,6 +661,12 @@ template <typename T> s3_status bind_impl(s3_plan *p, const s3_buffers *buf, voi
     const size_t need = layout<T>(p, nullptr, buf->x_nnz, buf->t_nnz, y_nnz, with_order, &temp_bytes);
     if (!ws || ws_bytes < need)
         return fail(p, S3_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    {
+        // set-up of the allocation-free entry point's memory on this device
+        void *sp = nullptr;
+        s3_status s = scratch_ptr(p, &sp);
+        if (s != S3_OK) return s;
+    }
     p->b = *buf;
     p->nX = buf->x_nnz;
     p->nT = buf->t_nnz;
@@ -742,14 +783,16 @@ template <typename T> s3_status loss_impl(s3_plan *p, double *out, hipStream_t s
 }
 
 // synchronous range check of caller-supplied SoA indices (not on the hot path)
+// flag: a device int32 (default: the plan's), cleared by a fill kernel
 s3_status check_indices(s3_plan *p, const int32_t *idx, int64_t nnz, int modes, const int64_t *lim,
-                        hipStream_t st) {
-    HIPCHK(p, hipMemsetAsync(p->flag + 2, 0, sizeof(int32_t), st));
+                        hipStream_t st, int32_t *flag = nullptr) {
+    if (!flag) flag = p->flag + 2;
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, flag, (int64_t)1, (int32_t)0);
     for (int n = 0; n < modes; ++n)
         hipLaunchKernelGGL(k_check_range, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, idx + (int64_t)n * nnz,
-                           nnz, lim[n], p->flag + 2);
+                           nnz, lim[n], flag);
     int32_t h = 0;
-    HIPCHK(p, hipMemcpyAsync(&h, p->flag + 2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(p, hipStreamSynchronize(st));
     if (h) return fail(p, S3_ERR_INDEX_RANGE, "an index lies outside its mode");
     return S3_OK;
@@ -884,7 +927,28 @@ s3_status s3_predict(s3_plan *p, const int32_t *idx, int64_t nnz, void *xhat, vo
         if (v != S3_OK) return v;
     }
     if (p->tsize == 8) pad_core<double>(p, st); else pad_core<float>(p, st);
-    p->ks.predict(p, idx, nnz, xhat, st);
+    p->ks.predict(p, idx, nnz, xhat, p->Gp, st);
+    HIPCHK(p, hipGetLastError());
+    return S3_OK;
+}
+
+s3_status s3_predict_noalloc(s3_plan *p, const int32_t *idx, int64_t nnz, void *xhat, void *stream) {
+    if (!p || (nnz > 0 && (!idx || !xhat)) || nnz < 0) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_predict_noalloc before s3_bind");
+    const size_t need = 256 + (size_t)p->KP * p->tsize;
+    if (need > kStaticScratchBytes)
+        return fail(p, S3_ERR_WORKSPACE, "the padded core needs %zu bytes of the %zu-byte static scratch", need,
+                    kStaticScratchBytes);
+    if (nnz == 0) return S3_OK;
+    void *sp = nullptr;
+    s3_status s = scratch_ptr(p, &sp);
+    if (s != S3_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    s = check_indices(p, idx, nnz, p->N, p->d.dims, st, (int32_t *)sp);
+    if (s != S3_OK) return s;
+    void *gp = (char *)sp + 256;
+    if (p->tsize == 8) pad_core<double>(p, st, gp); else pad_core<float>(p, st, gp);
+    p->ks.predict(p, idx, nnz, xhat, gp, st);
     HIPCHK(p, hipGetLastError());
     return S3_OK;
 }

@@ -185,6 +185,12 @@ class S3Plan:
         check(self.lib.s3_predict(self.h, _ptr(idx), idx.shape[1], _ptr(out), _stream()), self.h)
         return out
 
+    def predict_noalloc(self, idx: torch.Tensor, out: torch.Tensor) -> None:
+        """s3_predict_noalloc: predictions of the device entries idx (int32
+        [N, nnz]) into out, with no device memory taken from the workspace or
+        allocated (the library's static scratch array instead)."""
+        check(self.lib.s3_predict_noalloc(self.h, _ptr(idx), idx.shape[1], _ptr(out), _stream()), self.h)
+
     def predict_matrix(self, m: int, row, col) -> torch.Tensor:
         row = self._dev(row, torch.int32)
         col = self._dev(col, torch.int32)
