@@ -135,8 +135,12 @@ def main():
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--core", default="tucker", choices=["tucker", "cp"],
                     help="cp: the hyper-diagonal core (the CP special case), measured against the HBM roof")
-    ap.add_argument("--contraction", default="reuse", choices=["reuse", "naive"],
-                    help="naive: the per-entry contraction without reuse of partial products (ablation)")
+    ap.add_argument("--contraction", default="reuse", choices=["reuse", "naive", "matrix"],
+                    help="naive: the per-entry contraction without reuse of partial products (ablation); "
+                         "matrix: the dense part on the matrix cores")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"],
+                    help="bf16: FP32 master parameters, BF16 operands on the matrix cores (needs --contraction "
+                         "matrix)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
@@ -185,7 +189,7 @@ def main():
     n_updates = p.n_items
     log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {n_updates - p.n_train:,} matrix entries")
     order = item_order(p.n_items, args.seed, 0) if args.mode == "det" else None
-    plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", batch=args.batch, order=order, damping=True,
+    plan = S3Plan.from_problem(p, (U, G, V), dtype=args.dtype, batch=args.batch, order=order, damping=True,
                                round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows,
                                contraction=args.contraction, core=args.core)
     torch.cuda.synchronize()

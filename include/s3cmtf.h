@@ -104,6 +104,17 @@ enum { S3_DAMP_NONE = 0, S3_DAMP_CURVATURE = 1 };       /* s3_desc.damping */
 /* Per-entry contraction (s3_desc.contraction). */
 #define S3_CONTRACT_REUSE 0
 #define S3_CONTRACT_NAIVE 1
+#define S3_CONTRACT_MATRIX 2  /* the dense part on the matrix cores: the mode
+                                 products G x_1 u^(1) and G x_N u^(N) of 32
+                                 entries at a time as (J^(N-1) x J) . (J x 32)
+                                 products, the rest of Eq (8)'s contractions
+                                 reusing them on the vector units (Algorithm 3's
+                                 reuse of partial products); the core gradient
+                                 of each 256-entry tile on the matrix cores too.
+                                 Operands FP32 (S3_F32) or BF16 (S3_BF16), sums
+                                 in FP32.  Built for 3-way tensors with padded
+                                 rank 16 (ranks 13..16) and 4-way tensors with
+                                 padded rank 8 (ranks 5..8)                   */
 
 /* Core structure (s3_desc.core_kind). */
 #define S3_CORE_TUCKER 0   /* dense core J_1 x ... x J_N (Eq 4)             */
@@ -119,9 +130,14 @@ typedef struct {
     int32_t rank[S3_MAX_ORDER];          /* J_n                              */
     int32_t mat_mode[S3_MAX_MATRICES];   /* c_m, coupled tensor mode         */
     int64_t mat_cols[S3_MAX_MATRICES];   /* K_m                              */
-    int32_t dtype;                       /* S3_F64 or S3_F32 (S3_BF16 is
-                                            reserved and gives
-                                            S3_ERR_UNSUPPORTED)               */
+    int32_t dtype;                       /* S3_F64, S3_F32, or S3_BF16: FP32
+                                            values and parameters (the master
+                                            copies) whose contraction operands
+                                            are rounded to BF16 (round to
+                                            nearest even) as they are read;
+                                            needs S3_CONTRACT_MATRIX.  Loss,
+                                            RMSE, the row updates and the core
+                                            update stay FP32                  */
     int32_t damping;                     /* S3_DAMP_*                        */
     double eta0, mu, lambda_reg, lambda_m;
     int64_t batch;                       /* det mode: items per batch (>= 1) */
@@ -131,13 +147,16 @@ typedef struct {
                                             per-round hot tables (0: as many as
                                             the LDS budget allows, <= 256; -1:
                                             none, every row is updated at once) */
-    int32_t contraction;                 /* S3_CONTRACT_REUSE (default) or
+    int32_t contraction;                 /* S3_CONTRACT_REUSE (default; the
+                                            single pass on the vector units),
                                             S3_CONTRACT_NAIVE: the per-entry
                                             contraction without reuse of partial
                                             products (Algorithm 2's cost, an
                                             ablation of Lemma 4; N = 3 with
                                             J <= 4 or J = 10, N = 4 with J <= 2,
-                                            else S3_ERR_UNSUPPORTED)          */
+                                            else S3_ERR_UNSUPPORTED), or
+                                            S3_CONTRACT_MATRIX (above; FP32 or
+                                            BF16 only, Tucker core only)      */
     int32_t core_kind;                   /* S3_CORE_TUCKER (default) or
                                             S3_CORE_CP (then every rank must be
                                             equal, else S3_ERR_INVALID_ARG, and
@@ -145,8 +164,7 @@ typedef struct {
 } s3_desc;
 
 /* Device buffers handed to s3_bind.  Values and parameters are `double` for
- * S3_F64 and `float` for S3_F32.  The *_bf16 fields are reserved for a bf16
- * working-copy mode that this library does not provide; leave them null.   */
+ * S3_F64 and `float` for S3_F32 and S3_BF16.                               */
 typedef struct {
     const int32_t *x_idx;  const void *x_val;  int64_t x_nnz;   /* training */
     const int32_t *t_idx;  const void *t_val;  int64_t t_nnz;   /* held-out */
@@ -157,9 +175,6 @@ typedef struct {
     void *U[S3_MAX_ORDER];
     void *G;
     void *V[S3_MAX_MATRICES];
-    void *U_bf16[S3_MAX_ORDER];
-    void *G_bf16;
-    void *V_bf16[S3_MAX_MATRICES];
     /* det mode: the item order, a permutation of 0..n_items-1 (n_items =
      * x_nnz + sum y_nnz), int32.  May be null if det mode is never run.   */
     const int32_t *order;
@@ -279,11 +294,6 @@ s3_status s3_orthogonalize(s3_plan *plan, void *stream);
  * launch shape.  Needs s3_bind (else S3_ERR_STATE); sigma must be finite and
  * >= 0 (else S3_ERR_INVALID_ARG).  Asynchronous on stream.                 */
 s3_status s3_init_params(s3_plan *plan, uint64_t seed, double sigma, void *stream);
-
-/* Reserved for bf16 working copies of float masters.  This library has no
- * bf16 mode (S3_BF16 plans are rejected), so it always returns
- * S3_ERR_UNSUPPORTED (S3_ERR_INVALID_ARG for a null plan).                 */
-s3_status s3_sync_bf16(s3_plan *plan, void *stream);
 
 /* Turn per-launch timing of the dominant kernel (the tensor-entry kernel of
  * the epoch's mode) on or off; off by default.  When on, each such launch

@@ -22,14 +22,14 @@ S3_ERR_STATE = -7
 S3_F64, S3_F32, S3_BF16 = 0, 1, 2
 S3_DET_MINIBATCH, S3_LOCKFREE = 0, 1
 S3_DAMP_NONE, S3_DAMP_CURVATURE = 0, 1
-S3_CONTRACT_REUSE, S3_CONTRACT_NAIVE = 0, 1
+S3_CONTRACT_REUSE, S3_CONTRACT_NAIVE, S3_CONTRACT_MATRIX = 0, 1, 2
 S3_CORE_TUCKER, S3_CORE_CP = 0, 1
 
 # every function the header declares
 EXPORTS = [
     "s3_status_string", "s3_last_error", "s3_plan_create", "s3_plan_destroy", "s3_workspace_size",
     "s3_bind", "s3_epoch", "s3_det_batches", "s3_loss", "s3_rmse", "s3_predict", "s3_predict_noalloc", "s3_predict_matrix",
-    "s3_backward", "s3_export", "s3_orthogonalize", "s3_init_params", "s3_sync_bf16", "s3_set_profiling",
+    "s3_backward", "s3_export", "s3_orthogonalize", "s3_init_params", "s3_set_profiling",
     "s3_last_epoch_profile",
 ]
 
@@ -53,7 +53,6 @@ class S3Buffers(C.Structure):
         ("y_row", C.c_void_p * MAX_MATRICES), ("y_col", C.c_void_p * MAX_MATRICES),
         ("y_val", C.c_void_p * MAX_MATRICES), ("y_nnz", C.c_int64 * MAX_MATRICES),
         ("U", C.c_void_p * MAX_ORDER), ("G", C.c_void_p), ("V", C.c_void_p * MAX_MATRICES),
-        ("U_bf16", C.c_void_p * MAX_ORDER), ("G_bf16", C.c_void_p), ("V_bf16", C.c_void_p * MAX_MATRICES),
         ("order", C.c_void_p),
     ]
 
@@ -96,7 +95,6 @@ def load() -> C.CDLL:
         "s3_export": ([vp, i32, i32, C.POINTER(dbl), C.c_size_t, vp], i32),
         "s3_orthogonalize": ([vp, vp], i32),
         "s3_init_params": ([vp, C.c_uint64, dbl, vp], i32),
-        "s3_sync_bf16": ([vp, vp], i32),
         "s3_set_profiling": ([vp, i32], i32),
         "s3_last_epoch_profile": ([vp, C.POINTER(dbl), C.POINTER(i64)], i32),
     }

@@ -18,8 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libs3cmtf.so")
 SOURCES = ["s3cmtf.hip", "sets_f32_3.hip", "sets_f32_4.hip", "sets_f64.hip", "sets_cp.hip",
-           "sets_naive.hip"]
-HEADERS = ["common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "qr.hpp", "plan.hpp"]
+           "sets_naive.hip", "sets_mx.hip"]
+HEADERS = ["common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "mfma.hpp", "qr.hpp", "plan.hpp"]
 ARCH = os.environ.get("S3_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

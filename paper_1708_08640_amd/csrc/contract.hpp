@@ -273,6 +273,9 @@ template <int N, int JP, typename T, typename GP> S3_DEV T predict_cp(GP g, cons
 constexpr int kReuse = 0;  // single pass with reuse (above)
 constexpr int kNaive = 1;  // ablation: no reuse
 constexpr int kCP = 2;     // hyper-diagonal core
+constexpr int kMfma32 = 3; // dense part on the matrix cores, FP32 operands (mfma.hpp)
+constexpr int kMfma16 = 4; // dense part on the matrix cores, BF16 operands, FP32 sums
+constexpr bool is_mx(int ct) { return ct == kMfma32 || ct == kMfma16; }
 
 template <int CT, int N, int JP, typename T, typename GP>
 S3_DEV void contract_any(GP G, const T (&u)[N][JP], T (&w)[N][JP], T &xhat) {

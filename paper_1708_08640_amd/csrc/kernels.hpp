@@ -27,6 +27,7 @@
 
 #include "common.hpp"
 #include "contract.hpp"
+#include "mfma.hpp"
 
 namespace s3 {
 
@@ -656,6 +657,107 @@ S3_DEV void det_tensor_lane(const TensorArgs<T> &A, const int32_t *__restrict__ 
     }
 }
 
+// Tensor entries of one det block with the dense part of the contraction on
+// the matrix cores (mfma.hpp): 256 entries, one lane each, block blk = core
+// chunk blk.  Each wavefront stages its 64 entries' rows in LDS, contracts
+// them together and reads back x~ and w_n; the scratch row and the chunk's
+// core-gradient partial are those of det_tensor_lane (core gradient on the
+// FP32 or BF16 matrix cores, FP32 sums).
+template <int N, int JP, bool ADJ, int CT>
+S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict__ ids, int64_t nt,
+                          const float *__restrict__ Gp, float *__restrict__ scr, int64_t stride,
+                          const float *__restrict__ gx, float *__restrict__ part, float *__restrict__ part_curv,
+                          int64_t blk) {
+    using T = float;
+    constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
+    constexpr int SLOT = MfmaDims<N, JP>::SLOT;
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int SLOTS = kChunk * SLOT, QU = kChunk * JP + kChunk * (N - 1) * JP;
+    __shared__ __align__(16) float s_buf[SLOTS > QU ? SLOTS : QU];
+    __shared__ __align__(16) unsigned char s_g[mfma_core_bytes<N, JP, OP>()];
+    __shared__ float s_red[kChunk / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    mfma_stage_core<N, JP, OP>(Gp, s_g);
+    const int64_t s = blk * kChunk + tid;
+    const bool live = s < nt;
+    T u[N][JP];
+    int32_t rows[N];
+    int64_t e = 0;
+    if (live) {
+        e = ids[s];
+        load_rows<N, JP, T>(A, e, u, rows);
+    } else {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            rows[n] = 0;
+#pragma unroll
+            for (int k = 0; k < JP; ++k) u[n][k] = T(0);
+        }
+    }
+    T *slots = s_buf + (size_t)wv * kWave * SLOT;
+    T *mine = slots + (size_t)lane * SLOT;
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; k += 4)
+            *(s3_v4f_m *)(mine + n * JP + k) = s3_v4f_m{u[n][k], u[n][k + 1], u[n][k + 2], u[n][k + 3]};
+    __syncthreads();  // slots and the staged core
+    mfma_contract_wave<N, JP, OP>(slots, s_g);
+    __syncthreads();
+    T w[N][JP];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; k += 4) {
+            const s3_v4f_m t = *(const s3_v4f_m *)(mine + n * JP + k);
+            w[n][k] = t[0];
+            w[n][k + 1] = t[1];
+            w[n][k + 2] = t[2];
+            w[n][k + 3] = t[3];
+        }
+    const T xhat = mine[N * JP];
+    __syncthreads();  // s_buf is reused for the core-gradient operands
+    T q = T(0), curv = T(0);
+    if (live) {
+        const T xv = ADJ ? gx[e] : A.val[e];
+        constexpr bool train = !ADJ;
+        q = train ? -(xv - xhat) : xv;
+        T *out = scr + s * stride;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const T reg = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
+            T ww = T(0);
+#pragma unroll
+            for (int k = 0; k < JP; ++k) {
+                out[n * JP + k] = fmaT(q, w[n][k], reg * u[n][k]);
+                ww = fmaT(w[n][k], w[n][k], ww);
+            }
+            out[N * JP + n] = ww + reg;
+        }
+        curv = core_curv<kReuse, N, JP, T>(u);
+        out[stride - 2] = q;
+        out[stride - 1] = curv;
+    }
+    T *s_q = s_buf;
+    T *s_u = s_buf + kChunk * JP;
+#pragma unroll
+    for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+#pragma unroll
+    for (int n = 1; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_u[(tid * (N - 1) + n - 1) * JP + k] = u[n][k];
+    curv = wave_sum(curv);
+    if (lane == 0) s_red[wv] = curv;
+    __syncthreads();
+    if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kChunk>(s_q, s_u, part + blk * (JP * TAIL), kChunk);
+    else core_tile_mfma<N, JP>(s_q, s_u, part + blk * (JP * TAIL));
+    if (tid == 0) {
+        T c = T(0);
+        for (int x = 0; x < kChunk / kWave; ++x) c += s_red[x];
+        part_curv[blk] = c;
+    }
+}
+
 // One det batch's entries in one launch.  Blocks [0, t_blocks): the tensor
 // entries, block b = core chunk b (64 entries contracted by the block's four
 // wavefronts together for the FP32 reuse contraction, det_tensor_split; else
@@ -693,7 +795,10 @@ __global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const i
         if (s < d.n) det_matrix_entry(d, s, B.lambda_m, B.lambda_reg);
         return;
     }
-    if constexpr (det_split<T, CT>())
+    if constexpr (is_mx(CT)) {
+        if constexpr (mfma_shape<N, JP>() && std::is_same<T, float>::value)
+            det_tensor_mx<N, JP, ADJ, CT>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);
+    } else if constexpr (det_split<T, CT>())
         det_tensor_split<N, JP, ADJ>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk, bidx, bval, bstride);
     else
         det_tensor_lane<N, JP, T, ADJ, CT>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);

@@ -39,6 +39,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace s3 {
 
@@ -443,6 +444,156 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP, CT>())) void k_lf_tenso
         core[KP + 1] = cnt;
     }
     // the workgroup's hot-row table, written densely
+    __syncthreads();
+    T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
+    for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
+}
+
+// The same round kernel with the dense part of every entry's contraction
+// on the matrix cores (mfma.hpp): the core's operands are staged in LDS at
+// the start, each wavefront stages its 64 entries' rows, contracts them
+// together and reads back x~ and w_n; the per-entry updates, hot-row sums and
+// matrix tiles are those of k_lf_tensor.  The core gradient of the tile runs
+// on the FP32 matrix cores (FP32 operands) or the BF16 ones (BF16 operands),
+// summed in FP32 either way.  FP32 parameters (the master copies).
+template <int N, int JP, bool EXACT, int CT>
+__global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, const float *__restrict__ Gp,
+                                                           LFArgs<float> L, LFMatArgs<float> Y, int64_t n_tensor,
+                                                           float eta, float kappa) {
+    using T = float;
+    constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int KP = JP * TAIL;
+    constexpr int SLOT = MfmaDims<N, JP>::SLOT;
+    constexpr int GB = mfma_core_bytes<N, JP, OP>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if ((int64_t)blockIdx.x >= n_tensor) {
+        int64_t blk = (int64_t)blockIdx.x - n_tensor;
+        for (int m = 0; m < Y.M; ++m) {
+            if (blk < Y.n_blocks[m]) {
+                lf_matrix_tile<JP, T, EXACT>(Y, m, blk, L, eta, kappa, (T *)smem_raw);
+                return;
+            }
+            blk -= Y.n_blocks[m];
+        }
+        return;
+    }
+    constexpr int W = JP + 1;
+    constexpr int NWV = kTile / kWave;
+    void *s_g = smem_raw;                              // staged core operands
+    T *s_tab = (T *)(smem_raw + GB);                   // [N][H][W]
+    T *s_misc = s_tab + (size_t)N * L.H * W;
+    T *s_stage = s_misc + 4 * ((2 * NWV + 3) / 4);     // 16-byte aligned; [N][W][kTile] sorted hot rows,
+                                                       // before that the entry slots, after it:
+    T *s_q = s_stage;                                  // [kTile][JP]  q * u^(1)
+    T *s_u = s_q + kTile * JP;                         // [kTile][N - 1][JP]
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int tabn = N * L.H * W;
+    for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
+    mfma_stage_core<N, JP, OP>(Gp, s_g);
+
+    const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
+    const int64_t e = tile * kTile + tid;
+    const bool live = e < A.nnz;
+    T u[N][JP];
+    int32_t rows[N];
+    if (live) {
+        load_rows<N, JP, T, EXACT>(A, e, u, rows);
+    } else {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            rows[n] = 0;
+#pragma unroll
+            for (int k = 0; k < JP; ++k) u[n][k] = T(0);
+        }
+    }
+    // the wavefront's entry slots: rows in, x~ and w_n out
+    T *slots = s_stage + (size_t)wv * kWave * SLOT;
+    T *mine = slots + (size_t)lane * SLOT;
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; k += 4)
+            *(s3_v4f_m *)(mine + n * JP + k) = s3_v4f_m{u[n][k], u[n][k + 1], u[n][k + 2], u[n][k + 3]};
+    __syncthreads();  // slots and the staged core
+    mfma_contract_wave<N, JP, OP>(slots, s_g);
+    __syncthreads();
+    T w[N][JP];
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; k += 4) {
+            const s3_v4f_m t = *(const s3_v4f_m *)(mine + n * JP + k);
+            w[n][k] = t[0];
+            w[n][k + 1] = t[1];
+            w[n][k + 2] = t[2];
+            w[n][k + 3] = t[3];
+        }
+    const T xhat = mine[N * JP];
+    __syncthreads();  // the slots are reused for the hot-row staging below
+    T q = T(0), LG = T(0);
+    if (live) {
+        const T xv = A.val[e];
+        const uint2 ms = L.meta_slot[e];
+        q = -(xv - xhat);
+        LG = T(1);
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const T reg = L.meta_reg[(int64_t)n * A.nnz + e];
+            T ww = T(0), uu = T(0);
+#pragma unroll
+            for (int k = 0; k < JP; ++k) {
+                ww = fmaT(w[n][k], w[n][k], ww);
+                uu = fmaT(u[n][k], u[n][k], uu);
+            }
+            LG *= uu;
+            const T ell = ww + reg;
+            const int pos = lf_field(ms, n);
+            if (pos >= 0) {
+                T *t = s_stage + (size_t)n * W * kTile + pos;
+#pragma unroll
+                for (int k = 0; k < JP; ++k) t[k * kTile] = fmaT(q, w[n][k], reg * u[n][k]);
+                t[JP * kTile] = ell;
+            } else {
+                const T d = kappa * eta * ell;
+                const T step = eta / (d > T(1) ? d : T(1));
+                T *r = A.U[n] + (int64_t)rows[n] * (EXACT ? JP : A.J[n]);
+#pragma unroll
+                for (int k = 0; k < JP; ++k)
+                    if (EXACT || k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
+            }
+        }
+    }
+    {
+        const T lg = wave_sum(LG);
+        const uint64_t bal = __ballot(live);
+        if (lane == 0) {
+            s_misc[2 * wv] = lg;
+            s_misc[2 * wv + 1] = (T)__popcll(bal);
+        }
+    }
+    __syncthreads();
+    lf_chunk_pass<JP, N>(s_stage, s_tab, L.chunks + (size_t)tile * N * kTile, L.nchunks + tile * N, L.H);
+    __syncthreads();
+    T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
+#pragma unroll
+    for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+#pragma unroll
+    for (int n = 1; n < N; ++n)
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = u[n][k];
+    __syncthreads();
+    if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kTile>(s_q, s_u, core, kTile);
+    else core_tile_mfma<N, JP>(s_q, s_u, core);
+    if (tid == 0) {
+        T lg = T(0), cnt = T(0);
+        for (int x = 0; x < NWV; ++x) {
+            lg += s_misc[2 * x];
+            cnt += s_misc[2 * x + 1];
+        }
+        core[KP] = lg;
+        core[KP + 1] = cnt;
+    }
     __syncthreads();
     T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
     for (int i = tid; i < tabn; i += kTile) tab[i] = s_tab[i];
@@ -876,6 +1027,26 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
     }
     if (blocks <= 0) return;
     const size_t W = (size_t)JP + 1;
+    if constexpr (is_mx(CT)) {
+        if constexpr (mfma_shape<N, JP>() && std::is_same<T, float>::value) {
+            constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
+            // staged core, tables and misc (padded to 16 bytes), then the larger
+            // of the entry slots and the hot-row staging
+            const size_t stage = std::max((size_t)kTile * MfmaDims<N, JP>::SLOT, (size_t)N * kTile * W);
+            const size_t main = mfma_core_bytes<N, JP, OP>() +
+                                ((size_t)N * s.H * W + 4 * ((2 * (kTile / kWave) + 3) / 4) + stage) * sizeof(T);
+            const size_t smem = std::max(main, (size_t)2 * (s.H * W + kTile * W) * sizeof(T));
+            static bool attr = false;  // per instantiation: allow more than 64 KiB of dynamic LDS
+            if (!attr) {
+                (void)hipFuncSetAttribute((const void *)k_lf_tensor_mx<N, JP, EXACT, CT>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                attr = true;
+            }
+            hipExtLaunchKernelGGL((k_lf_tensor_mx<N, JP, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile),
+                                  (uint32_t)smem, st, e0, e1, 0, A, Gp, L, Y, count, eta, (T)(N + 1));
+        }
+        return;
+    }
     const size_t smem = std::max((size_t)N * (s.H * W + kTile * W) + 2 * (kTile / kWave),
                                  (size_t)2 * (s.H * W + kTile * W)) * sizeof(T);
     // e0/e1 (profiling, may be null) take the dispatch's own start and end

@@ -1,0 +1,331 @@
+// Dense part of the per-entry contraction on the matrix cores.
+//
+// For 64 entries (one per lane of a wavefront) whose factor rows are staged
+// in LDS, two mode products of the core (Eq 4's contraction taken one mode
+// at a time, Definition 1):
+//   T1_e = G x_1 u^(1)_e     (a tensor over modes 2..N)
+//   TN_e = G x_N u^(N)_e     (a tensor over modes 1..N-1)
+// are (tail x JP) . (JP x 32 entries) products on the matrix cores: the core,
+// matricised with the other modes as rows, is the A operand (staged in LDS in
+// the instruction's lane order) and the 32 entries' rows of the contracted
+// mode are B.  An output column (one entry) lands in lanes j and j + 32, each
+// with half of the tail.  The rest runs on the VALU in those two lanes:
+//   from T1: x~ and w_2 .. w_N (T1 is contracted with the remaining rows and
+//            every partial contraction is reused, as in Algorithm 3),
+//   from TN: w_1 = TN contracted with u^(2) .. u^(N-1).
+// The tail order of each lane half is chosen so that every leave-one-out
+// vector except two is complete inside a lane; those two and x~ are summed
+// with the partner lane (lane ^ 32).  Cost per entry: 4 J^N multiply-adds on
+// the matrix cores (instead of 2 J^N on the VALU) and about 3 J^(N-1) on
+// the VALU.
+//
+// Operands: OP = kOpF32 uses v_mfma_f32_32x32x2f32 (FP32 inputs and sums);
+// OP = kOpBF16 uses v_mfma_f32_32x32x8bf16_1k (inputs rounded to BF16, round
+// to nearest even, FP32 sums).
+// Shapes: N = 4 with JP = 8 (tail 512, 16 tiles of 32 rows) and N = 3 with
+// JP = 16 (tail 256, 8 tiles).
+//
+// Lane layouts (checked on gfx950): 32x32x2f32: A[i][k] in lane i + 32 k,
+// B[k][j] in lane j + 32 k; 32x32x8bf16_1k: A[i][k] in lane i + 32 (k / 4),
+// slot k % 4 (B alike); output D[i][j] in lane j + 32 ((i / 4) % 2),
+// register 4 (i / 8) + i % 4.
+#pragma once
+#include "common.hpp"
+
+namespace s3 {
+
+constexpr int kOpF32 = 0;
+constexpr int kOpBF16 = 1;
+
+typedef float s3_v16f __attribute__((ext_vector_type(16)));
+typedef float s3_v4f_m __attribute__((ext_vector_type(4)));
+typedef short s3_v4s __attribute__((ext_vector_type(4)));
+
+template <int N, int JP> constexpr bool mfma_shape() { return (N == 4 && JP == 8) || (N == 3 && JP == 16); }
+
+template <int N, int JP> struct MfmaDims {
+    static constexpr int TL = (N == 3) ? JP * JP : JP * JP * JP;  // tail of one product
+    static constexpr int NQ = TL / 32;                            // 32-row tiles
+    static constexpr int SLOT = N * JP + 4;                       // floats per entry slot in LDS
+};
+
+template <int OP, int JP> struct MfmaOp {
+    static constexpr int NC = (OP == kOpBF16) ? JP / 8 : JP / 2;  // instructions per tile (K chunks)
+    static constexpr int V = (OP == kOpBF16) ? 4 : 1;             // operand values per lane per chunk
+};
+
+// bytes of the staged core operands (both products)
+template <int N, int JP, int OP> constexpr int mfma_core_bytes() {
+    return 2 * MfmaDims<N, JP>::NQ * kWave * MfmaOp<OP, JP>::NC * MfmaOp<OP, JP>::V * (OP == kOpBF16 ? 2 : 4);
+}
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN)
+S3_DEV unsigned short bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Tail position held by output register r of tile q in lane half h.  With
+// (x, y, z) the tail's mode indices (modes 2..N for T1, 1..N-1 for TN):
+//   N = 4: pair pi = 2 q + r / 8, x = 4 h + pi / 8, y = pi % 8, z = r % 8, so
+//          half h owns x in [4h, 4h + 4) with every y and z;
+//   N = 3: x = 8 h + q, y = r, so half h owns x in [8h, 8h + 8).
+template <int N, int JP> S3_DEV int mfma_tail(int q, int h, int r) {
+    if constexpr (N == 4) {
+        const int pi = 2 * q + (r >> 3);
+        return ((4 * h + (pi >> 3)) * 8 + (pi & 7)) * 8 + (r & 7);
+    } else {
+        return (8 * h + q) * 16 + r;
+    }
+}
+
+// Stage the core operands of both products into LDS (all threads of the
+// block; Gp is the zero-padded JP^N core, row-major).  Layout: product,
+// tile, lane, then the lane's chunks and values, so that a lane reads its
+// whole A operand of a tile with one or two wide loads.
+template <int N, int JP, int OP>
+S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *s_g) {
+    using D = MfmaDims<N, JP>;
+    using O = MfmaOp<OP, JP>;
+    constexpr int total = 2 * D::NQ * kWave * O::NC * O::V;
+    for (int x = threadIdx.x; x < total; x += blockDim.x) {
+        const int v = x % O::V;
+        int t = x / O::V;
+        const int c = t % O::NC;
+        t /= O::NC;
+        const int lane = t % kWave;
+        t /= kWave;
+        const int q = t % D::NQ, prod = t / D::NQ;
+        const int i = lane & 31, kh = lane >> 5;
+        const int k = (OP == kOpBF16) ? 8 * c + 4 * kh + v : 2 * c + kh;
+        const int h = (i >> 2) & 1, r = 4 * (i >> 3) + (i & 3);
+        const int tail = mfma_tail<N, JP>(q, h, r);
+        const float g = (prod == 0) ? Gp[k * D::TL + tail] : Gp[tail * JP + k];
+        if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[x] = bf16_rne(g);
+        else ((float *)s_g)[x] = g;
+    }
+}
+
+// B operand chunks of one entry row (the lane half kh takes its K values)
+template <int OP, int JP> struct MfmaB {
+    typename std::conditional<OP == kOpBF16, s3_v4s, float>::type c[MfmaOp<OP, JP>::NC];
+};
+
+template <int OP, int JP> S3_DEV MfmaB<OP, JP> mfma_b_of(const float *row, int kh) {
+    MfmaB<OP, JP> b;
+#pragma unroll
+    for (int c = 0; c < MfmaOp<OP, JP>::NC; ++c) {
+        if constexpr (OP == kOpBF16) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b.c[c][v] = (short)bf16_rne(row[8 * c + 4 * kh + v]);
+        } else {
+            b.c[c] = row[2 * c + kh];
+        }
+    }
+    return b;
+}
+
+// One 32 x 32 output tile: product prod, tile q
+template <int N, int JP, int OP>
+S3_DEV s3_v16f mfma_tile(const void *s_g, int prod, int q, int lane, const MfmaB<OP, JP> &b) {
+    using D = MfmaDims<N, JP>;
+    using O = MfmaOp<OP, JP>;
+    s3_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int base = ((prod * D::NQ + q) * kWave + lane) * O::NC * O::V;
+    if constexpr (OP == kOpBF16) {
+        const s3_v4s *a = (const s3_v4s *)((const unsigned short *)s_g + base);
+#pragma unroll
+        for (int c = 0; c < O::NC; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[c], b.c[c], acc, 0, 0, 0);
+    } else {
+        const float *a = (const float *)s_g + base;
+        float av[O::NC];
+#pragma unroll
+        for (int c = 0; c < O::NC; c += 4) {
+            const s3_v4f_m t = *(const s3_v4f_m *)(a + c);  // 16-byte aligned: NC is a multiple of 4
+            av[c] = t[0];
+            av[c + 1] = t[1];
+            av[c + 2] = t[2];
+            av[c + 3] = t[3];
+        }
+#pragma unroll
+        for (int c = 0; c < O::NC; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[c], b.c[c], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// The wavefront's 64 entries: slot s (s = 0..63) of `slots` holds entry s's
+// rows u^(1) | ... | u^(N) (JP each, zero padded) and receives, in place,
+// w_1 | ... | w_N | x~.  Every lane of the wavefront must call it.
+template <int N, int JP, int OP>
+S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
+    static_assert(mfma_shape<N, JP>(), "matrix-core contraction: N = 4 with JP = 8, or N = 3 with JP = 16");
+    using D = MfmaDims<N, JP>;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int j = lane & 31, h = lane >> 5;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+        float *slot = slots + (32 * pass + j) * D::SLOT;
+        const MfmaB<OP, JP> bfirst = mfma_b_of<OP, JP>(slot, h);
+        const MfmaB<OP, JP> blast = mfma_b_of<OP, JP>(slot + (N - 1) * JP, h);
+        if constexpr (N == 4) {
+            float b[8], c[8], d[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                b[k] = slot[8 + k];
+                c[k] = slot[16 + k];
+                d[k] = slot[24 + k];
+            }
+            float bh[4];  // u^(2) at this half's mode-2 indices 4h .. 4h + 3
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bh[k] = h ? b[4 + k] : b[k];
+            float R[4] = {0.f, 0.f, 0.f, 0.f}, w1l[4] = {0.f, 0.f, 0.f, 0.f};
+            float w3p[8], w4p[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) { w3p[k] = 0.f; w4p[k] = 0.f; }
+#pragma unroll
+            for (int q = 0; q < D::NQ; ++q) {
+                // T1 tile: (j2, j3, j4) = (4h + pi / 8, pi % 8, r % 8), pi = 2q + r / 8
+                const s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, q, lane, bfirst);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int pi = 2 * q + s, jl = pi >> 3, j3 = pi & 7;
+                    const float bc = bh[jl] * c[j3];
+                    float S = 0.f;
+#pragma unroll
+                    for (int z = 0; z < 8; ++z) {
+                        S = fmaf(t1[8 * s + z], d[z], S);           // (T1 x_4 u4)[j2][j3]
+                        w4p[z] = fmaf(t1[8 * s + z], bc, w4p[z]);   // (T1 x_2 u2 x_3 u3)[j4]
+                    }
+                    R[jl] = fmaf(S, c[j3], R[jl]);                   // w_2[j2]
+                    w3p[j3] = fmaf(S, bh[jl], w3p[j3]);              // w_3[j3] (this half's j2)
+                }
+                // TN tile: (j1, j2, j3) = (4h + pi / 8, pi % 8, r % 8)
+                const s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, q, lane, blast);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int pi = 2 * q + s, jl = pi >> 3, j2 = pi & 7;
+                    float P = 0.f;
+#pragma unroll
+                    for (int z = 0; z < 8; ++z) P = fmaf(tn[8 * s + z], c[z], P);
+                    w1l[jl] = fmaf(P, b[j2], w1l[jl]);               // w_1[j1]
+                }
+            }
+            float xp = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xp = fmaf(R[k], bh[k], xp);
+            const float x = xp + __shfl_xor(xp, 32, kWave);
+            // this lane keeps indices 4h .. 4h + 3 of w_3 and w_4; the partner
+            // sends its partial sums at those indices
+            float w3o[4], w4o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float s3 = h ? w3p[k] : w3p[4 + k], s4 = h ? w4p[k] : w4p[4 + k];
+                const float m3 = h ? w3p[4 + k] : w3p[k], m4 = h ? w4p[4 + k] : w4p[k];
+                w3o[k] = m3 + __shfl_xor(s3, 32, kWave);
+                w4o[k] = m4 + __shfl_xor(s4, 32, kWave);
+            }
+            // results in place (the pair's rows are no longer read)
+            *(s3_v4f_m *)(slot + 4 * h) = s3_v4f_m{w1l[0], w1l[1], w1l[2], w1l[3]};
+            *(s3_v4f_m *)(slot + 8 + 4 * h) = s3_v4f_m{R[0], R[1], R[2], R[3]};
+            *(s3_v4f_m *)(slot + 16 + 4 * h) = s3_v4f_m{w3o[0], w3o[1], w3o[2], w3o[3]};
+            *(s3_v4f_m *)(slot + 24 + 4 * h) = s3_v4f_m{w4o[0], w4o[1], w4o[2], w4o[3]};
+            if (h == 0) slot[32] = x;
+        } else {
+            float b[16], c[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                b[k] = slot[16 + k];
+                c[k] = slot[32 + k];
+            }
+            float bh[8];  // u^(2) at this half's indices 8h .. 8h + 7
+#pragma unroll
+            for (int k = 0; k < 8; ++k) bh[k] = h ? b[8 + k] : b[k];
+            float R[8], w1l[8], w3p[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w3p[k] = 0.f;
+            float xp = 0.f;
+#pragma unroll
+            for (int q = 0; q < D::NQ; ++q) {
+                // T1 tile: (j2, j3) = (8h + q, r)
+                const s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, q, lane, bfirst);
+                float S = 0.f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    S = fmaf(t1[r], c[r], S);                  // w_2[j2]
+                    w3p[r] = fmaf(t1[r], bh[q], w3p[r]);       // w_3[j3] (this half's j2)
+                }
+                R[q] = S;
+                xp = fmaf(S, bh[q], xp);
+                // TN tile: (j1, j2) = (8h + q, r)
+                const s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, q, lane, blast);
+                float P = 0.f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) P = fmaf(tn[r], b[r], P);
+                w1l[q] = P;                                    // w_1[j1]
+            }
+            const float x = xp + __shfl_xor(xp, 32, kWave);
+            float w3o[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float s3 = h ? w3p[k] : w3p[8 + k];
+                const float m3 = h ? w3p[8 + k] : w3p[k];
+                w3o[k] = m3 + __shfl_xor(s3, 32, kWave);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k += 4) {
+                *(s3_v4f_m *)(slot + 8 * h + k) = s3_v4f_m{w1l[k], w1l[k + 1], w1l[k + 2], w1l[k + 3]};
+                *(s3_v4f_m *)(slot + 16 + 8 * h + k) = s3_v4f_m{R[k], R[k + 1], R[k + 2], R[k + 3]};
+                *(s3_v4f_m *)(slot + 32 + 8 * h + k) = s3_v4f_m{w3o[k], w3o[k + 1], w3o[k + 2], w3o[k + 3]};
+            }
+            if (h == 0) slot[48] = x;
+        }
+    }
+}
+
+// Core gradient of a chunk of K entries on the BF16 matrix cores (FP32
+// sums): C[j1][tau] = sum_t (q u^(1))_t[j1] (u^(2) o ... o u^(N))_t[tau], as
+// (16 x K) x (K x 16 n-tiles) products with v_mfma_f32_16x16x16bf16_1k
+// (A[i][k] in lane i + 16 (k / 4), slot k % 4; D[4 (l / 16) + r][l % 16] in
+// lane l, register r).  Same operands and output as core_tile_mfma.
+template <int N, int JP, int K>
+S3_DEV void core_tile_mfma_bf16(const float *s_q, const float *s_u, float *core, int nthreads) {
+    constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
+    constexpr int NT = (TAIL + 15) / 16;
+    const int NW = nthreads / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int i16 = lane & 15, kq = lane >> 4;
+    for (int nt = wv; nt < NT; nt += NW) {  // uniform over the wave
+        const int tau = 16 * nt + i16;
+        const bool tv = tau < TAIL;
+        int tj[N - 1];
+        int r = tv ? tau : 0;
+#pragma unroll
+        for (int n = N - 2; n >= 0; --n) { tj[n] = r % JP; r /= JP; }
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            s3_v4s a, b;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = k0 + 4 * kq + v;
+                const float av = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
+                float bv = s_u[(t * (N - 1)) * JP + tj[0]];
+#pragma unroll
+                for (int n = 1; n < N - 1; ++n) bv *= s_u[(t * (N - 1) + n) * JP + tj[n]];
+                a[v] = (short)bf16_rne(av);
+                b[v] = (short)bf16_rne(tv ? bv : 0.f);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        if (tv) {
+#pragma unroll
+            for (int r2 = 0; r2 < 4; ++r2) {
+                const int j1 = 4 * kq + r2;
+                if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[r2];
+            }
+        }
+    }
+}
+
+}  // namespace s3

@@ -208,5 +208,6 @@ bool pick_reuse_f32_4(int JP, KernelSet *ks);
 bool pick_reuse_f64(int N, int JP, KernelSet *ks);
 bool pick_cp(bool f64, int N, int JP, KernelSet *ks);
 bool pick_naive(bool f64, int N, int JP, KernelSet *ks);
+bool pick_mx(bool bf16, int N, int JP, KernelSet *ks);
 
 }  // namespace s3

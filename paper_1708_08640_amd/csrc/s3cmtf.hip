@@ -41,7 +41,8 @@ s3_status fail(s3_plan *p, s3_status st, const char *fmt, ...) {
             return fail(plan, S3_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
     } while (0)
 
-bool pick_set_any(bool f64, int N, int JP, KernelSet *ks, bool naive, bool cp) {
+bool pick_set_any(bool f64, int N, int JP, KernelSet *ks, bool naive, bool cp, bool matrix, bool bf16) {
+    if (matrix) return !f64 && pick_mx(bf16, N, JP, ks);
     if (cp) return pick_cp(f64, N, JP, ks);
     if (naive) return pick_naive(f64, N, JP, ks);
     if (f64) return pick_reuse_f64(N, JP, ks);
@@ -302,12 +303,15 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     const s3_desc &d = *desc;
     if (d.order < 3 || d.order > S3_MAX_ORDER) return S3_ERR_UNSUPPORTED;
     if (d.n_mat < 0 || d.n_mat > S3_MAX_MATRICES) return S3_ERR_INVALID_ARG;
-    // FP64 and FP32 only: bf16 copies would add traffic to every row update
-    // (the FP32 master must still be read), and the contraction is on the VALU
-    if (d.dtype != S3_F64 && d.dtype != S3_F32) return S3_ERR_UNSUPPORTED;
+    if (d.dtype != S3_F64 && d.dtype != S3_F32 && d.dtype != S3_BF16) return S3_ERR_UNSUPPORTED;
     if (d.damping != S3_DAMP_NONE && d.damping != S3_DAMP_CURVATURE) return S3_ERR_INVALID_ARG;
     if (d.batch < 1 || d.round_items < 1 || d.hot_rows < -1 || d.hot_rows > 256) return S3_ERR_INVALID_ARG;
-    if (d.contraction != S3_CONTRACT_REUSE && d.contraction != S3_CONTRACT_NAIVE) return S3_ERR_INVALID_ARG;
+    if (d.contraction != S3_CONTRACT_REUSE && d.contraction != S3_CONTRACT_NAIVE &&
+        d.contraction != S3_CONTRACT_MATRIX)
+        return S3_ERR_INVALID_ARG;
+    // BF16 operands exist only on the matrix cores; the matrix cores take FP32 or BF16
+    if (d.dtype == S3_BF16 && d.contraction != S3_CONTRACT_MATRIX) return S3_ERR_UNSUPPORTED;
+    if (d.dtype == S3_F64 && d.contraction == S3_CONTRACT_MATRIX) return S3_ERR_UNSUPPORTED;
     if (d.core_kind != S3_CORE_TUCKER && d.core_kind != S3_CORE_CP) return S3_ERR_INVALID_ARG;
     if (d.core_kind == S3_CORE_CP) {
         for (int n = 1; n < d.order; ++n)
@@ -342,7 +346,8 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **out) {
     p->tsize = (d.dtype == S3_F64) ? 8 : 4;
     const bool naive = d.contraction == S3_CONTRACT_NAIVE;
     const bool cp = d.core_kind == S3_CORE_CP;
-    const bool ok = pick_set_any(d.dtype == S3_F64, p->N, JP, &p->ks, naive, cp);
+    const bool ok = pick_set_any(d.dtype == S3_F64, p->N, JP, &p->ks, naive, cp,
+                                 d.contraction == S3_CONTRACT_MATRIX, d.dtype == S3_BF16);
     if (!ok) {
         delete p;
         return S3_ERR_UNSUPPORTED;
@@ -1117,12 +1122,6 @@ s3_status s3_init_params(s3_plan *p, uint64_t seed, double sigma, void *stream) 
     for (int m = 0; m < p->M; ++m) one(p->b.V[m], p->d.mat_cols[m] * p->d.rank[p->d.mat_mode[m]], p->N + 1 + m);
     HIPCHK(p, hipGetLastError());
     return S3_OK;
-}
-
-s3_status s3_sync_bf16(s3_plan *p, void *stream) {
-    if (!p) return S3_ERR_INVALID_ARG;
-    (void)stream;
-    return fail(p, S3_ERR_UNSUPPORTED, "bf16 working copies are not built in this library");
 }
 
 s3_status s3_set_profiling(s3_plan *p, int32_t on) {

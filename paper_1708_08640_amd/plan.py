@@ -11,7 +11,12 @@ import torch
 from . import _abi
 from ._abi import check, load
 
-_DTYPES = {"f64": (_abi.S3_F64, torch.float64), "f32": (_abi.S3_F32, torch.float32)}
+# bf16: FP32 values and parameters (the master copies), BF16 contraction
+# operands on the matrix cores
+_DTYPES = {"f64": (_abi.S3_F64, torch.float64), "f32": (_abi.S3_F32, torch.float32),
+           "bf16": (_abi.S3_BF16, torch.float32)}
+_CONTRACTIONS = {"reuse": _abi.S3_CONTRACT_REUSE, "naive": _abi.S3_CONTRACT_NAIVE,
+                 "matrix": _abi.S3_CONTRACT_MATRIX}
 _MODES = {"det": _abi.S3_DET_MINIBATCH, "lockfree": _abi.S3_LOCKFREE}
 
 
@@ -60,9 +65,9 @@ class S3Plan:
         d.round_items = int(round_items)
         d.seed = int(seed)
         d.hot_rows = int(hot_rows)
-        if contraction not in ("reuse", "naive"):
-            raise ValueError("contraction must be 'reuse' or 'naive'")
-        d.contraction = _abi.S3_CONTRACT_NAIVE if contraction == "naive" else _abi.S3_CONTRACT_REUSE
+        if contraction not in _CONTRACTIONS:
+            raise ValueError(f"contraction must be one of {list(_CONTRACTIONS)}")
+        d.contraction = _CONTRACTIONS[contraction]
         if core not in ("tucker", "cp"):
             raise ValueError("core must be 'tucker' or 'cp'")
         d.core_kind = _abi.S3_CORE_CP if core == "cp" else _abi.S3_CORE_TUCKER

@@ -25,7 +25,7 @@ def setup(name, dtype="f64", batch=512, damping=False, order_seed=123, round_ite
     U, G, V = init_params(cfg)
     if core == "cp":  # the hyper-diagonal part of the same seeded core
         G = np.array([G[(r,) * cfg.order] for r in range(cfg.ranks[0])])
-    if dtype == "f32":
+    if dtype in ("f32", "bf16"):  # bf16 plans keep FP32 parameters (the master copies)
         r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
         U, G, V = [r(u) for u in U], r(G), [r(v) for v in V]
     order = item_order(p.n_items, order_seed, 0)

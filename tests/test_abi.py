@@ -56,13 +56,17 @@ def _desc(_abi, **kw):
     (dict(order=2), -3),
     (dict(order=5), -3),
     (dict(dtype=7), -3),
-    (dict(dtype=2), -3),  # bf16 is reserved, not provided
+    (dict(dtype=2), -3),  # bf16 operands exist only in the matrix-core contraction
+    (dict(dtype=2, contraction=2), -3),  # which is not built for padded rank 10
+    (dict(dtype=0, contraction=2, rank=(16, 16, 16)), -3),  # nor for FP64
     (dict(rank=(10, 10, 40)), -3),
     (dict(batch=0), -1),
     (dict(eta0=-1.0), -1),
     (dict(n_mat=9), -1),
     (dict(mat_mode=(3, 0, 0, 0)), -1),
-    (dict(contraction=2), -1),
+    (dict(contraction=3), -1),
+    (dict(contraction=2), -3),  # matrix cores: padded rank 16 (3-way) or 8 (4-way) only
+    (dict(core_kind=1, contraction=2, rank=(16, 16, 16)), -3),
     (dict(contraction=1, rank=(8, 8, 8)), -3),  # no naive kernels for J = 8
     (dict(core_kind=2), -1),
     (dict(core_kind=1, rank=(10, 10, 8)), -1),  # CP needs equal ranks
