@@ -665,7 +665,7 @@ S3_DEV void det_tensor_lane(const TensorArgs<T> &A, const int32_t *__restrict__ 
 // FP32 or BF16 matrix cores, FP32 sums).
 template <int N, int JP, bool ADJ, int CT>
 S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict__ ids, int64_t nt,
-                          const float *__restrict__ Gp, float *__restrict__ scr, int64_t stride,
+                          const void *__restrict__ g_fmt, float *__restrict__ scr, int64_t stride,
                           const float *__restrict__ gx, float *__restrict__ part, float *__restrict__ part_curv,
                           int64_t blk) {
     using T = float;
@@ -677,7 +677,7 @@ S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict_
     __shared__ __align__(16) unsigned char s_g[mfma_core_bytes<N, JP, OP>()];
     __shared__ float s_red[kChunk / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    mfma_stage_core<N, JP, OP>(Gp, s_g);
+    mfma_load_core<N, JP, OP>(g_fmt, s_g);
     const int64_t s = blk * kChunk + tid;
     const bool live = s < nt;
     T u[N][JP];
@@ -738,19 +738,23 @@ S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict_
         out[stride - 2] = q;
         out[stride - 1] = curv;
     }
-    T *s_q = s_buf;
-    T *s_u = s_buf + kChunk * JP;
-#pragma unroll
-    for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
-#pragma unroll
-    for (int n = 1; n < N; ++n)
-#pragma unroll
-        for (int k = 0; k < JP; ++k) s_u[(tid * (N - 1) + n - 1) * JP + k] = u[n][k];
     curv = wave_sum(curv);
     if (lane == 0) s_red[wv] = curv;
-    __syncthreads();
-    if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kChunk>(s_q, s_u, part + blk * (JP * TAIL), kChunk);
-    else core_tile_mfma<N, JP>(s_q, s_u, part + blk * (JP * TAIL));
+    if constexpr (N == 4) {
+        core_grad_mx4<OP>(q, u, s_buf, part + blk * (JP * TAIL));
+    } else {
+        T *s_q = s_buf;
+        T *s_u = s_buf + kChunk * JP;
+#pragma unroll
+        for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+#pragma unroll
+        for (int n = 1; n < N; ++n)
+#pragma unroll
+            for (int k = 0; k < JP; ++k) s_u[(tid * (N - 1) + n - 1) * JP + k] = u[n][k];
+        __syncthreads();
+        if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kChunk>(s_q, s_u, part + blk * (JP * TAIL), kChunk);
+        else core_tile_mfma<N, JP>(s_q, s_u, part + blk * (JP * TAIL));
+    }
     if (tid == 0) {
         T c = T(0);
         for (int x = 0; x < kChunk / kWave; ++x) c += s_red[x];
@@ -776,14 +780,18 @@ S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict_
 // regulariser).  The mode is a template flag and the entry's value is loaded
 // before the contraction: with a run-time choice between two loads after it
 // the compiler front-loads every scalar core load and spills them.
+// two waves per SIMD for the matrix-core form (its LDS allows two blocks per CU)
+template <int CT> constexpr int det_min_waves() { return is_mx(CT) ? 2 : 1; }
+
 template <int N, int JP, typename T, bool ADJ, int CT = kReuse>
-__global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const int32_t *__restrict__ ids,
+__global__ __launch_bounds__(kChunk, det_min_waves<CT>()) void k_det_entries(TensorArgs<T> A, const int32_t *__restrict__ ids,
                                                         int64_t nt, int64_t t_blocks, const T *__restrict__ Gp,
                                                         T *__restrict__ scr, int64_t stride,
                                                         const T *__restrict__ gx, T *__restrict__ part,
                                                         T *__restrict__ part_curv, DetMatArgs<T> B,
                                                         const int32_t *__restrict__ bidx,
-                                                        const T *__restrict__ bval, int64_t bstride) {
+                                                        const T *__restrict__ bval, int64_t bstride,
+                                                        const void *__restrict__ g_fmt) {
     const int64_t blk = blockIdx.x;
     const int tid = threadIdx.x;
     if (blk >= t_blocks) {
@@ -797,7 +805,7 @@ __global__ __launch_bounds__(kChunk) void k_det_entries(TensorArgs<T> A, const i
     }
     if constexpr (is_mx(CT)) {
         if constexpr (mfma_shape<N, JP>() && std::is_same<T, float>::value)
-            det_tensor_mx<N, JP, ADJ, CT>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk);
+            det_tensor_mx<N, JP, ADJ, CT>(A, ids, nt, g_fmt, scr, stride, gx, part, part_curv, blk);
     } else if constexpr (det_split<T, CT>())
         det_tensor_split<N, JP, ADJ>(A, ids, nt, Gp, scr, stride, gx, part, part_curv, blk, bidx, bval, bstride);
     else

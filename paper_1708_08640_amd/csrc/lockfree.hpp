@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP, CT>())) void k_lf_tenso
 // on the FP32 matrix cores (FP32 operands) or the BF16 ones (BF16 operands),
 // summed in FP32 either way.  FP32 parameters (the master copies).
 template <int N, int JP, bool EXACT, int CT>
-__global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, const float *__restrict__ Gp,
+__global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, const void *__restrict__ g_fmt,
                                                            LFArgs<float> L, LFMatArgs<float> Y, int64_t n_tensor,
                                                            float eta, float kappa) {
     using T = float;
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int tabn = N * L.H * W;
     for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
-    mfma_stage_core<N, JP, OP>(Gp, s_g);
+    mfma_load_core<N, JP, OP>(g_fmt, s_g);
 
     const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
     const int64_t e = tile * kTile + tid;
@@ -576,15 +576,19 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
     lf_chunk_pass<JP, N>(s_stage, s_tab, L.chunks + (size_t)tile * N * kTile, L.nchunks + tile * N, L.H);
     __syncthreads();
     T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
+    if constexpr (N == 4) {
+        core_grad_mx4<OP>(q, u, s_stage, core);
+    } else {
 #pragma unroll
-    for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+        for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
 #pragma unroll
-    for (int n = 1; n < N; ++n)
+        for (int n = 1; n < N; ++n)
 #pragma unroll
-        for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = u[n][k];
-    __syncthreads();
-    if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kTile>(s_q, s_u, core, kTile);
-    else core_tile_mfma<N, JP>(s_q, s_u, core);
+            for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = u[n][k];
+        __syncthreads();
+        if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kTile>(s_q, s_u, core, kTile);
+        else core_tile_mfma<N, JP>(s_q, s_u, core);
+    }
     if (tid == 0) {
         T lg = T(0), cnt = T(0);
         for (int x = 0; x < NWV; ++x) {
@@ -996,7 +1000,8 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
 
 template <int N, int JP, typename T, bool EXACT, int CT = kReuse>
 void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
-                            T eta, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+                            T eta, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                            const void *g_fmt = nullptr) {
     LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
     LFMatArgs<T> Y{};
     Y.M = s.M;
@@ -1043,7 +1048,7 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
                 attr = true;
             }
             hipExtLaunchKernelGGL((k_lf_tensor_mx<N, JP, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile),
-                                  (uint32_t)smem, st, e0, e1, 0, A, Gp, L, Y, count, eta, (T)(N + 1));
+                                  (uint32_t)smem, st, e0, e1, 0, A, g_fmt, L, Y, count, eta, (T)(N + 1));
         }
         return;
     }

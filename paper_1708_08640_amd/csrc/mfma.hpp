@@ -85,7 +85,7 @@ template <int N, int JP> S3_DEV int mfma_tail(int q, int h, int r) {
 // tile, lane, then the lane's chunks and values, so that a lane reads its
 // whole A operand of a tile with one or two wide loads.
 template <int N, int JP, int OP>
-S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *s_g) {
+S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *__restrict__ s_g) {
     using D = MfmaDims<N, JP>;
     using O = MfmaOp<OP, JP>;
     constexpr int total = 2 * D::NQ * kWave * O::NC * O::V;
@@ -104,6 +104,25 @@ S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *s_g) {
         const float g = (prod == 0) ? Gp[k * D::TL + tail] : Gp[tail * JP + k];
         if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[x] = bf16_rne(g);
         else ((float *)s_g)[x] = g;
+    }
+}
+
+// The operand layout above written once per core value (one block; the
+// round and batch kernels then copy it into LDS with wide loads).
+template <int N, int JP, int OP>
+__global__ __launch_bounds__(256) void k_mx_format(const float *__restrict__ Gp, void *__restrict__ out) {
+    mfma_stage_core<N, JP, OP>(Gp, out);
+}
+
+// Copy the formatted operands into LDS (all threads of the block)
+template <int N, int JP, int OP> S3_DEV void mfma_load_core(const void *__restrict__ g, void *__restrict__ s_g) {
+    constexpr int n16 = mfma_core_bytes<N, JP, OP>() / 16;
+    const uint4 *src = (const uint4 *)g;
+    uint4 *dst = (uint4 *)s_g;
+#pragma unroll
+    for (int i = 0; i < (n16 + 255) / 256; ++i) {
+        const int x = i * 256 + threadIdx.x;
+        if (x < n16) dst[x] = src[x];
     }
 }
 
@@ -280,6 +299,88 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
             }
             if (h == 0) slot[48] = x;
         }
+    }
+}
+
+// Core gradient of the block's 256 entries for a 4-way core with JP = 8:
+//   C[j1 j2][j3 j4] = sum_t (q u^(1) o u^(2))_t[j1 j2] (u^(3) o u^(4))_t[j3 j4],
+// a (64 x 256) . (256 x 64) product.  Every entry's two 64-value outer
+// products are staged in LDS (entry-major rows, padded against bank
+// conflicts), a part of the entries at a time; wavefront w computes the 32 x 32
+// output tile (w / 2, w % 2).  BF16 operands: v_mfma_f32_32x32x8bf16_1k on
+// halves of 128 entries; FP32: v_mfma_f32_32x32x2f32 on quarters of 64.
+// Sums in FP32.  `buf` needs 36,864 bytes, 16-byte aligned; core receives
+// the 4,096 values (row-major j1 j2 j3 j4, the padded core layout).
+template <int OP>
+S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__restrict__ core) {
+    constexpr int kPart = (OP == kOpBF16) ? 128 : 64;   // entries staged at a time
+    constexpr int kRow = (OP == kOpBF16) ? 136 : 132;   // staged row: 128 values + padding
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int rb = wv >> 1, cb = wv & 1, i = lane & 31, kh = lane >> 5;
+    float pa[8], pc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        pa[k] = q * u[0][k];
+        pc[k] = u[2][k];
+    }
+    s3_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int part = 0; part < 256 / kPart; ++part) {  // the block's 256 entries
+        const int tl = tid - part * kPart;
+        if (tl >= 0 && tl < kPart) {
+            if constexpr (OP == kOpBF16) {
+                unsigned short *row = (unsigned short *)buf + (size_t)tl * kRow;
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    uint32_t pw[4], qw[4];
+#pragma unroll
+                    for (int b = 0; b < 8; b += 2) {
+                        pw[b / 2] = (uint32_t)bf16_rne(pa[a] * u[1][b]) | ((uint32_t)bf16_rne(pa[a] * u[1][b + 1]) << 16);
+                        qw[b / 2] = (uint32_t)bf16_rne(pc[a] * u[3][b]) | ((uint32_t)bf16_rne(pc[a] * u[3][b + 1]) << 16);
+                    }
+                    *(uint4 *)(row + 8 * a) = make_uint4(pw[0], pw[1], pw[2], pw[3]);
+                    *(uint4 *)(row + 64 + 8 * a) = make_uint4(qw[0], qw[1], qw[2], qw[3]);
+                }
+            } else {
+                float *row = buf + (size_t)tl * kRow;
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    *(s3_v4f_m *)(row + 8 * a) = s3_v4f_m{pa[a] * u[1][0], pa[a] * u[1][1], pa[a] * u[1][2], pa[a] * u[1][3]};
+                    *(s3_v4f_m *)(row + 8 * a + 4) = s3_v4f_m{pa[a] * u[1][4], pa[a] * u[1][5], pa[a] * u[1][6], pa[a] * u[1][7]};
+                    *(s3_v4f_m *)(row + 64 + 8 * a) = s3_v4f_m{pc[a] * u[3][0], pc[a] * u[3][1], pc[a] * u[3][2], pc[a] * u[3][3]};
+                    *(s3_v4f_m *)(row + 68 + 8 * a) = s3_v4f_m{pc[a] * u[3][4], pc[a] * u[3][5], pc[a] * u[3][6], pc[a] * u[3][7]};
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (OP == kOpBF16) {
+            const unsigned short *sb = (const unsigned short *)buf;
+#pragma unroll 4
+            for (int k0 = 0; k0 < kPart; k0 += 8) {
+                s3_v4s a, b;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int t = k0 + 4 * kh + v;
+                    a[v] = (short)sb[(size_t)t * kRow + 32 * rb + i];
+                    b[v] = (short)sb[(size_t)t * kRow + 64 + 32 * cb + i];
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            }
+        } else {
+#pragma unroll 4
+            for (int k0 = 0; k0 < kPart; k0 += 2) {
+                const int t = k0 + kh;
+                const float a = buf[(size_t)t * kRow + 32 * rb + i];
+                const float b = buf[(size_t)t * kRow + 64 + 32 * cb + i];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+        core[(size_t)(32 * rb + row) * 64 + 32 * cb + i] = acc[r];
     }
 }
 

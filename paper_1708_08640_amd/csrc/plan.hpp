@@ -63,6 +63,7 @@ struct KernelSet {
     void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
     void (*predict)(s3_plan *, const int32_t *, int64_t, void *, const void *, hipStream_t);  // Gp: padded core
     void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t, hipEvent_t, hipEvent_t);
+    void (*mx_format)(s3_plan *, hipStream_t);  // matrix-core sets: core operands from Gp into mx_g
     int det_chunk;  // tensor entries per det block and core chunk
 };
 
@@ -80,6 +81,7 @@ struct s3_plan {
     int32_t *cnt[S3_MAX_ORDER] = {};
     int32_t *cntV[S3_MAX_MATRICES] = {};
     void *Gp = nullptr;
+    void *mx_g = nullptr;  // the padded core in the matrix-core operand layout
     int32_t *flag = nullptr;
     double *red = nullptr;  // reduction partials
     int64_t n_red = 0;
@@ -157,11 +159,13 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
         if (gx)
             hipExtLaunchKernelGGL((k_det_entries<N, JP, T, true, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
                                   e0, e1, 0, a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
-                                  (const T *)gx, (T *)p->part, (T *)p->part_curv, B, bidx, bval, p->n_items);
+                                  (const T *)gx, (T *)p->part, (T *)p->part_curv, B, bidx, bval, p->n_items,
+                                  (const void *)p->mx_g);
         else
             hipExtLaunchKernelGGL((k_det_entries<N, JP, T, false, CT>), dim3((unsigned)blocks), dim3(kChunk), 0, st,
                                   e0, e1, 0, a, ids, nt, t_blocks, (const T *)p->Gp, (T *)p->scr, p->t_stride,
-                                  (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B, bidx, bval, p->n_items);
+                                  (const T *)nullptr, (T *)p->part, (T *)p->part_curv, B, bidx, bval, p->n_items,
+                                  (const void *)p->mx_g);
     }
     // FP64 Tucker core partials (the other cores are formed in det_entries)
     static void core_partial(s3_plan *p, const int32_t *ids, int64_t nt, hipStream_t st) {
@@ -189,16 +193,24 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
                           hipEvent_t e1) {
         if (p->exact)
             lockfree_tensor_launch<N, JP, T, true, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                                          (const T *)p->Gp, first, count, (T)eta, st, e0, e1);
+                                                          (const T *)p->Gp, first, count, (T)eta, st, e0, e1,
+                                                          p->mx_g);
         else
             lockfree_tensor_launch<N, JP, T, false, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
-                                                           (const T *)p->Gp, first, count, (T)eta, st, e0, e1);
+                                                           (const T *)p->Gp, first, count, (T)eta, st, e0, e1,
+                                                           p->mx_g);
+    }
+    static void mx_format(s3_plan *p, hipStream_t st) {
+        if constexpr (is_mx(CT) && mfma_shape<N, JP>() && std::is_same<T, float>::value) {
+            constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
+            hipLaunchKernelGGL((k_mx_format<N, JP, OP>), dim3(1), dim3(256), 0, st, (const float *)p->Gp, p->mx_g);
+        }
     }
 };
 
 template <int N, int JP, typename T, int CT = kReuse> KernelSet make_set() {
     using I = Impl<N, JP, T, CT>;
-    return KernelSet{&I::det_entries, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor,
+    return KernelSet{&I::det_entries, &I::core_partial, &I::sq_err, &I::predict, &I::lf_tensor, &I::mx_format,
                      det_chunk<T, CT>()};
 }
 

@@ -224,6 +224,7 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
             if (e0 && e1) p->pev_used += 2;
             else e0 = e1 = nullptr;
         }
+        if (t_blocks > 0) p->ks.mx_format(p, st);  // the core as the last batch left it
         p->ks.det_entries(p, p->sorted_ids + t0, nt, t_blocks, adj ? gx : nullptr, &B, blocks, st, e0, e1);
     }
     if (t_blocks > 0) p->ks.core_partial(p, p->sorted_ids + t0, nt, st);
@@ -427,6 +428,7 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
     for (int n = 0; n < N; ++n) p->cnt[n] = c.take<int32_t>((size_t)p->d.dims[n]);
     for (int m = 0; m < M; ++m) p->cntV[m] = c.take<int32_t>((size_t)p->d.mat_cols[m]);
     p->Gp = c.take<T>((size_t)p->KP);
+    p->mx_g = c.take<char>((size_t)32 * 1024);  // the largest matrix-core operand layout (FP32, 4,096 values x 2)
     p->flag = c.take<int32_t>(16);
     p->n_red = std::max<int64_t>({(int64_t)2 * kReduceBlocks, sq_blocks(x_nnz), sq_blocks(t_nnz)});
     p->red = c.take<double>((size_t)p->n_red);
@@ -891,6 +893,7 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
                 if (e0 && e1) p->pev_used += 2;
                 else e0 = e1 = nullptr;
             }
+            p->ks.mx_format(p, s_);  // the core as the last round left it
             p->ks.lf_tensor(p, f, c, e, s_, e0, e1);
         };
         if (p->tsize == 8) {
