@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"],
                     help="bf16: FP32 master parameters, BF16 operands on the matrix cores (needs --contraction "
                          "matrix)")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="profiling runs only: entry counts of the tensor and of the sparse matrices times this "
+                         "(same dimensions, ranks and rounds)")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
@@ -181,6 +184,12 @@ def main():
         scaling_sweep(args)
         return
     cfg = get_config(args.config)
+    if args.scale != 1.0:
+        import dataclasses
+        mats = tuple(m if m.nnz == cfg.dims[m.mode] * m.cols else dataclasses.replace(m, nnz=int(m.nnz * args.scale))
+                     for m in cfg.matrices)
+        cfg = cfg.scaled(name=f"{cfg.name}_x{args.scale:g}", nnz=int(cfg.nnz * args.scale), matrices=mats,
+                         description=cfg.description + f"; entry counts x {args.scale:g} (profiling)")
     log(f"generating {cfg.name}: {cfg.description}")
     p = make_problem(cfg)
     U, G, V = init_params(cfg)

@@ -363,7 +363,7 @@ S3_DEV void det_matrix_entry(const DetMatrix<T> &d, int64_t s, T lambda_m, T lam
 typedef float s3_v4f __attribute__((ext_vector_type(4)));
 
 template <int N, int JP, int K = kChunk>
-S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
+S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core, bool add = false) {
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
     constexpr int NT = (TAIL + 15) / 16;                 // n-tiles
     constexpr int NW = kChunk / kWave;                    // waves of the 256-thread block
@@ -404,7 +404,10 @@ S3_DEV void core_tile_mfma(const float *s_q, const float *s_u, float *core) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j1 = 4 * kq + r;
-            if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[q][r];
+            if (j1 < JP) {
+                float *c = core + (size_t)j1 * TAIL + tau;
+                *c = add ? *c + acc[q][r] : acc[q][r];
+            }
         }
     }
 }

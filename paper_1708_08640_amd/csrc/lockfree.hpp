@@ -44,6 +44,7 @@
 namespace s3 {
 
 constexpr int kTile = 256;
+constexpr int64_t kMxResident = 512;  // tensor workgroups of the matrix-core round kernel (2 per CU)
 
 template <typename T> struct LFArgs {
     const int32_t *hot_slot[kMaxN + kMaxM];  // row -> slot in [0, H) or -1
@@ -104,7 +105,9 @@ template <> S3_DEV uint32_t lf_cold<uint32_t>() { return 0xffffffffu; }
 
 // G groups of one tile: s_stage [G][JP + 1][kTile] (sorted positions),
 // s_tab [G][H][JP + 1] (zeroed); between two barriers
-template <int JP, int G, typename T>
+// ACC: the table already holds earlier tiles' sums (a workgroup that runs
+// several tiles), so a whole run is added to it rather than stored.
+template <int JP, int G, typename T, bool ACC = false>
 S3_DEV void lf_chunk_pass(const T *s_stage, T *s_tab, const uint32_t *chunks, const int32_t *nchunks, int H) {
     constexpr int W = JP + 1;
     int base[G + 1];
@@ -124,8 +127,12 @@ S3_DEV void lf_chunk_pass(const T *s_stage, T *s_tab, const uint32_t *chunks, co
         for (int j = 0; j < kRun; ++j)
             if (j < len) sum += src[j];
         T *dst = s_tab + ((size_t)g * H + slot) * W + k;
-        if ((d >> 20) & 1) *dst = sum;
-        else atomicAdd(dst, sum);
+        if ((d >> 20) & 1) {
+            if constexpr (ACC) *dst += sum;
+            else *dst = sum;
+        } else {
+            atomicAdd(dst, sum);
+        }
     }
 }
 
@@ -450,16 +457,20 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP, CT>())) void k_lf_tenso
 }
 
 // The same round kernel with the dense part of every entry's contraction
-// on the matrix cores (mfma.hpp): the core's operands are staged in LDS at
-// the start, each wavefront stages its 64 entries' rows, contracts them
-// together and reads back x~ and w_n; the per-entry updates, hot-row sums and
-// matrix tiles are those of k_lf_tensor.  The core gradient of the tile runs
-// on the FP32 matrix cores (FP32 operands) or the BF16 ones (BF16 operands),
-// summed in FP32 either way.  FP32 parameters (the master copies).
+// on the matrix cores (mfma.hpp).  A tensor workgroup runs several of the
+// round's tiles in turn (tiles b, b + n_tensor, ...): the core's operands are
+// staged in LDS once, and the hot-row tables, the core-gradient sums and the
+// curvature sums carry over from tile to tile, so each workgroup writes one
+// table and one core partial per round.  Per tile, each wavefront stages its
+// 64 entries' rows, contracts them together and reads back x~ and w_n; the
+// per-entry updates, hot-row sums and the matrix tiles (one per workgroup, in
+// the blocks after the tensor ones) are those of k_lf_tensor.  The core
+// gradient runs on the FP32 or BF16 matrix cores, summed in FP32.  FP32
+// parameters (the master copies).
 template <int N, int JP, bool EXACT, int CT>
 __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, const void *__restrict__ g_fmt,
                                                            LFArgs<float> L, LFMatArgs<float> Y, int64_t n_tensor,
-                                                           float eta, float kappa) {
+                                                           int64_t n_tiles, float eta, float kappa) {
     using T = float;
     constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
@@ -484,119 +495,132 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
     T *s_tab = (T *)(smem_raw + GB);                   // [N][H][W]
     T *s_misc = s_tab + (size_t)N * L.H * W;
     T *s_stage = s_misc + 4 * ((2 * NWV + 3) / 4);     // 16-byte aligned; [N][W][kTile] sorted hot rows,
-                                                       // before that the entry slots, after it:
-    T *s_q = s_stage;                                  // [kTile][JP]  q * u^(1)
-    T *s_u = s_q + kTile * JP;                         // [kTile][N - 1][JP]
+                                                       // before that the entry slots, after it the
+                                                       // core-gradient operands
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int tabn = N * L.H * W;
     for (int i = tid; i < tabn; i += kTile) s_tab[i] = T(0);
     mfma_load_core<N, JP, OP>(g_fmt, s_g);
-
-    const int64_t tile = lf_perm(L.tile_base + blockIdx.x, L.pa, L.pb, L.n_tiles);
-    const int64_t e = tile * kTile + tid;
-    const bool live = e < A.nnz;
-    T u[N][JP];
-    int32_t rows[N];
-    if (live) {
-        load_rows<N, JP, T, EXACT>(A, e, u, rows);
-    } else {
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            rows[n] = 0;
-#pragma unroll
-            for (int k = 0; k < JP; ++k) u[n][k] = T(0);
-        }
-    }
-    // the wavefront's entry slots: rows in, x~ and w_n out
-    T *slots = s_stage + (size_t)wv * kWave * SLOT;
-    T *mine = slots + (size_t)lane * SLOT;
-#pragma unroll
-    for (int n = 0; n < N; ++n)
-#pragma unroll
-        for (int k = 0; k < JP; k += 4)
-            *(s3_v4f_m *)(mine + n * JP + k) = s3_v4f_m{u[n][k], u[n][k + 1], u[n][k + 2], u[n][k + 3]};
-    __syncthreads();  // slots and the staged core
-    mfma_contract_wave<N, JP, OP>(slots, s_g);
-    __syncthreads();
-    T w[N][JP];
-#pragma unroll
-    for (int n = 0; n < N; ++n)
-#pragma unroll
-        for (int k = 0; k < JP; k += 4) {
-            const s3_v4f_m t = *(const s3_v4f_m *)(mine + n * JP + k);
-            w[n][k] = t[0];
-            w[n][k + 1] = t[1];
-            w[n][k + 2] = t[2];
-            w[n][k + 3] = t[3];
-        }
-    const T xhat = mine[N * JP];
-    __syncthreads();  // the slots are reused for the hot-row staging below
-    T q = T(0), LG = T(0);
-    if (live) {
-        const T xv = A.val[e];
-        const uint2 ms = L.meta_slot[e];
-        q = -(xv - xhat);
-        LG = T(1);
-#pragma unroll
-        for (int n = 0; n < N; ++n) {
-            const T reg = L.meta_reg[(int64_t)n * A.nnz + e];
-            T ww = T(0), uu = T(0);
-#pragma unroll
-            for (int k = 0; k < JP; ++k) {
-                ww = fmaT(w[n][k], w[n][k], ww);
-                uu = fmaT(u[n][k], u[n][k], uu);
-            }
-            LG *= uu;
-            const T ell = ww + reg;
-            const int pos = lf_field(ms, n);
-            if (pos >= 0) {
-                T *t = s_stage + (size_t)n * W * kTile + pos;
-#pragma unroll
-                for (int k = 0; k < JP; ++k) t[k * kTile] = fmaT(q, w[n][k], reg * u[n][k]);
-                t[JP * kTile] = ell;
-            } else {
-                const T d = kappa * eta * ell;
-                const T step = eta / (d > T(1) ? d : T(1));
-                T *r = A.U[n] + (int64_t)rows[n] * (EXACT ? JP : A.J[n]);
-#pragma unroll
-                for (int k = 0; k < JP; ++k)
-                    if (EXACT || k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
-            }
-        }
-    }
-    {
-        const T lg = wave_sum(LG);
-        const uint64_t bal = __ballot(live);
-        if (lane == 0) {
-            s_misc[2 * wv] = lg;
-            s_misc[2 * wv + 1] = (T)__popcll(bal);
-        }
-    }
-    __syncthreads();
-    lf_chunk_pass<JP, N>(s_stage, s_tab, L.chunks + (size_t)tile * N * kTile, L.nchunks + tile * N, L.H);
-    __syncthreads();
     T *core = L.core_out + (size_t)blockIdx.x * (KP + 2);
-    if constexpr (N == 4) {
-        core_grad_mx4<OP>(q, u, s_stage, core);
-    } else {
+    s3_v16f cacc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    T lg_tot = T(0), cnt_tot = T(0);  // thread 0: curvature and entry counts of its tiles
+    bool first = true;
+
+#pragma unroll 1
+    for (int64_t it = blockIdx.x; it < n_tiles; it += n_tensor) {  // uniform over the block
+        const int64_t tile = lf_perm(L.tile_base + it, L.pa, L.pb, L.n_tiles);
+        const int64_t e = tile * kTile + tid;
+        const bool live = e < A.nnz;
+        T u[N][JP];
+        int32_t rows[N];
+        if (live) {
+            load_rows<N, JP, T, EXACT>(A, e, u, rows);
+        } else {
 #pragma unroll
-        for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+            for (int n = 0; n < N; ++n) {
+                rows[n] = 0;
 #pragma unroll
-        for (int n = 1; n < N; ++n)
-#pragma unroll
-            for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = u[n][k];
-        __syncthreads();
-        if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kTile>(s_q, s_u, core, kTile);
-        else core_tile_mfma<N, JP>(s_q, s_u, core);
-    }
-    if (tid == 0) {
-        T lg = T(0), cnt = T(0);
-        for (int x = 0; x < NWV; ++x) {
-            lg += s_misc[2 * x];
-            cnt += s_misc[2 * x + 1];
+                for (int k = 0; k < JP; ++k) u[n][k] = T(0);
+            }
         }
-        core[KP] = lg;
-        core[KP + 1] = cnt;
+        // the wavefront's entry slots: rows in, x~ and w_n out
+        T *slots = s_stage + (size_t)wv * kWave * SLOT;
+        T *mine = slots + (size_t)lane * SLOT;
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int k = 0; k < JP; k += 4)
+                *(s3_v4f_m *)(mine + n * JP + k) = s3_v4f_m{u[n][k], u[n][k + 1], u[n][k + 2], u[n][k + 3]};
+        __syncthreads();  // slots (and, first time, the staged core and zeroed tables)
+        mfma_contract_wave<N, JP, OP>(slots, s_g);
+        __syncthreads();
+        T w[N][JP];
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+#pragma unroll
+            for (int k = 0; k < JP; k += 4) {
+                const s3_v4f_m t = *(const s3_v4f_m *)(mine + n * JP + k);
+                w[n][k] = t[0];
+                w[n][k + 1] = t[1];
+                w[n][k + 2] = t[2];
+                w[n][k + 3] = t[3];
+            }
+        const T xhat = mine[N * JP];
+        __syncthreads();  // the slots are reused for the hot-row staging below
+        T q = T(0), LG = T(0);
+        if (live) {
+            const T xv = A.val[e];
+            const uint2 ms = L.meta_slot[e];
+            q = -(xv - xhat);
+            LG = T(1);
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                const T reg = L.meta_reg[(int64_t)n * A.nnz + e];
+                T ww = T(0), uu = T(0);
+#pragma unroll
+                for (int k = 0; k < JP; ++k) {
+                    ww = fmaT(w[n][k], w[n][k], ww);
+                    uu = fmaT(u[n][k], u[n][k], uu);
+                }
+                LG *= uu;
+                const T ell = ww + reg;
+                const int pos = lf_field(ms, n);
+                if (pos >= 0) {
+                    T *t = s_stage + (size_t)n * W * kTile + pos;
+#pragma unroll
+                    for (int k = 0; k < JP; ++k) t[k * kTile] = fmaT(q, w[n][k], reg * u[n][k]);
+                    t[JP * kTile] = ell;
+                } else {
+                    const T d = kappa * eta * ell;
+                    const T step = eta / (d > T(1) ? d : T(1));
+                    T *r = A.U[n] + (int64_t)rows[n] * (EXACT ? JP : A.J[n]);
+#pragma unroll
+                    for (int k = 0; k < JP; ++k)
+                        if (EXACT || k < A.J[n]) r[k] = u[n][k] - step * fmaT(q, w[n][k], reg * u[n][k]);
+                }
+            }
+        }
+        {
+            const T lg = wave_sum(LG);
+            const uint64_t bal = __ballot(live);
+            if (lane == 0) {
+                s_misc[2 * wv] = lg;
+                s_misc[2 * wv + 1] = (T)__popcll(bal);
+            }
+        }
+        __syncthreads();
+        lf_chunk_pass<JP, N, T, true>(s_stage, s_tab, L.chunks + (size_t)tile * N * kTile, L.nchunks + tile * N,
+                                      L.H);
+        __syncthreads();
+        if (tid == 0) {
+            for (int x = 0; x < NWV; ++x) {
+                lg_tot += s_misc[2 * x];
+                cnt_tot += s_misc[2 * x + 1];
+            }
+        }
+        if constexpr (N == 4) {
+            core_grad_mx4_acc<OP>(q, u, s_stage, cacc);  // ends with a barrier
+        } else {
+            T *s_q = s_stage;                   // [kTile][JP]  q * u^(1)
+            T *s_u = s_q + kTile * JP;          // [kTile][N - 1][JP]
+#pragma unroll
+            for (int k = 0; k < JP; ++k) s_q[tid * JP + k] = q * u[0][k];
+#pragma unroll
+            for (int n = 1; n < N; ++n)
+#pragma unroll
+                for (int k = 0; k < JP; ++k) s_u[((size_t)tid * (N - 1) + (n - 1)) * JP + k] = u[n][k];
+            __syncthreads();
+            // this workgroup's own core partial: stored by the first tile, added to after
+            if constexpr (OP == kOpBF16) core_tile_mfma_bf16<N, JP, kTile>(s_q, s_u, core, kTile, !first);
+            else core_tile_mfma<N, JP, kChunk>(s_q, s_u, core, !first);
+            __syncthreads();
+        }
+        first = false;
+    }
+    if constexpr (N == 4) core_grad_mx4_store(cacc, core);
+    if (tid == 0) {
+        core[KP] = lg_tot;
+        core[KP + 1] = cnt_tot;
     }
     __syncthreads();
     T *tab = L.tab_out + (size_t)blockIdx.x * tabn;
@@ -998,10 +1022,11 @@ template <typename T> LFArgs<T> lf_args(const LockFreeState &s, int64_t n_tiles,
     return L;
 }
 
+// Returns the number of tensor workgroups launched (the round's partial tables).
 template <int N, int JP, typename T, bool EXACT, int CT = kReuse>
-void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
-                            T eta, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
-                            const void *g_fmt = nullptr) {
+int64_t lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *Gp, int64_t first, int64_t count,
+                               T eta, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                               const void *g_fmt = nullptr) {
     LFArgs<T> L = lf_args<T>(s, s.t_tiles, first, (T *)s.tab_t, (T *)s.core_t);
     LFMatArgs<T> Y{};
     Y.M = s.M;
@@ -1030,10 +1055,15 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
         Y.gv[m] = N + m;
         blocks += s.m_count[m];
     }
-    if (blocks <= 0) return;
+    if (blocks <= 0) return count;
     const size_t W = (size_t)JP + 1;
     if constexpr (is_mx(CT)) {
         if constexpr (mfma_shape<N, JP>() && std::is_same<T, float>::value) {
+            // tensor workgroups: as many tiles each as two resident workgroups
+            // per CU need to cover the round, spread evenly
+            const int64_t per = std::max<int64_t>(1, (count + kMxResident - 1) / kMxResident);
+            const int64_t nwg = (count + per - 1) / per;
+            blocks = blocks - count + nwg;
             constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
             // staged core, tables and misc (padded to 16 bytes), then the larger
             // of the entry slots and the hot-row staging
@@ -1048,15 +1078,17 @@ void lockfree_tensor_launch(LockFreeState &s, const TensorArgs<T> &A, const T *G
                 attr = true;
             }
             hipExtLaunchKernelGGL((k_lf_tensor_mx<N, JP, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile),
-                                  (uint32_t)smem, st, e0, e1, 0, A, g_fmt, L, Y, count, eta, (T)(N + 1));
+                                  (uint32_t)smem, st, e0, e1, 0, A, g_fmt, L, Y, nwg, count, eta, (T)(N + 1));
+            return nwg;
         }
-        return;
+        return count;
     }
     const size_t smem = std::max((size_t)N * (s.H * W + kTile * W) + 2 * (kTile / kWave),
                                  (size_t)2 * (s.H * W + kTile * W)) * sizeof(T);
     // e0/e1 (profiling, may be null) take the dispatch's own start and end
     hipExtLaunchKernelGGL((k_lf_tensor<N, JP, T, EXACT, CT>), dim3((unsigned)blocks), dim3(kTile), (uint32_t)smem, st,
                           e0, e1, 0, A, Gp, L, Y, count, eta, (T)(N + 1));
+    return count;
 }
 
 inline uint64_t splitmix64(uint64_t &x) {
@@ -1103,7 +1135,7 @@ s3_status lockfree_epoch(LockFreeState &s, const s3_desc &d, int epoch, double e
             s.mpb[m] = mpb[m];
             s.apply.nwg_m[m] = s.m_count[m];
         }
-        tensor_round(t0, t1 - t0, eta, st);  // tensor and matrix tiles, one launch
+        s.apply.nwg_t = tensor_round(t0, t1 - t0, eta, st);  // tensor and matrix tiles, one launch
         const int64_t blocks = (int64_t)(N + M) * s.H + (s.KP + 15) / 16;
         const int64_t grid = (blocks + kXcds - 1) / kXcds * kXcds;
         auto kern = (N == 3) ? k_lf_apply<3, T> : k_lf_apply<4, T>;

@@ -59,11 +59,16 @@ template <int N, int JP, int OP> constexpr int mfma_core_bytes() {
     return 2 * MfmaDims<N, JP>::NQ * kWave * MfmaOp<OP, JP>::NC * MfmaOp<OP, JP>::V * (OP == kOpBF16 ? 2 : 4);
 }
 
-// FP32 -> BF16, round to nearest even (NaN stays NaN)
-S3_DEV unsigned short bf16_rne(float x) {
-    const uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+// Two FP32 values to a BF16 pair (round to nearest even; one
+// v_cvt_pk_bf16_f32), low half first
+typedef __bf16 s3_bf2 __attribute__((ext_vector_type(2)));
+S3_DEV uint32_t bf16x2(float lo, float hi) {
+    const s3_bf2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+S3_DEV s3_v4s bf16x4(float a, float b, float c, float d) {
+    const uint32_t lo = bf16x2(a, b), hi = bf16x2(c, d);
+    return s3_v4s{(short)(lo & 0xffffu), (short)(lo >> 16), (short)(hi & 0xffffu), (short)(hi >> 16)};
 }
 
 // Tail position held by output register r of tile q in lane half h.  With
@@ -80,8 +85,8 @@ template <int N, int JP> S3_DEV int mfma_tail(int q, int h, int r) {
     }
 }
 
-// Stage the core operands of both products into LDS (all threads of the
-// block; Gp is the zero-padded JP^N core, row-major).  Layout: product,
+// Stage the core operands of both products (all threads of the grid; Gp is
+// the zero-padded JP^N core, row-major).  Layout: product,
 // tile, lane, then the lane's chunks and values, so that a lane reads its
 // whole A operand of a tile with one or two wide loads.
 template <int N, int JP, int OP>
@@ -89,7 +94,7 @@ S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *__restrict__ s_g
     using D = MfmaDims<N, JP>;
     using O = MfmaOp<OP, JP>;
     constexpr int total = 2 * D::NQ * kWave * O::NC * O::V;
-    for (int x = threadIdx.x; x < total; x += blockDim.x) {
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
         const int v = x % O::V;
         int t = x / O::V;
         const int c = t % O::NC;
@@ -102,13 +107,13 @@ S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *__restrict__ s_g
         const int h = (i >> 2) & 1, r = 4 * (i >> 3) + (i & 3);
         const int tail = mfma_tail<N, JP>(q, h, r);
         const float g = (prod == 0) ? Gp[k * D::TL + tail] : Gp[tail * JP + k];
-        if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[x] = bf16_rne(g);
+        if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[x] = (unsigned short)(bf16x2(g, 0.f) & 0xffffu);
         else ((float *)s_g)[x] = g;
     }
 }
 
-// The operand layout above written once per core value (one block; the
-// round and batch kernels then copy it into LDS with wide loads).
+// The operand layout above written once per core value, one element per
+// thread (the round and batch kernels then copy it into LDS with wide loads).
 template <int N, int JP, int OP>
 __global__ __launch_bounds__(256) void k_mx_format(const float *__restrict__ Gp, void *__restrict__ out) {
     mfma_stage_core<N, JP, OP>(Gp, out);
@@ -136,8 +141,8 @@ template <int OP, int JP> S3_DEV MfmaB<OP, JP> mfma_b_of(const float *row, int k
 #pragma unroll
     for (int c = 0; c < MfmaOp<OP, JP>::NC; ++c) {
         if constexpr (OP == kOpBF16) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) b.c[c][v] = (short)bf16_rne(row[8 * c + 4 * kh + v]);
+            const float *r = row + 8 * c + 4 * kh;
+            b.c[c] = bf16x4(r[0], r[1], r[2], r[3]);
         } else {
             b.c[c] = row[2 * c + kh];
         }
@@ -202,10 +207,17 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
             float w3p[8], w4p[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) { w3p[k] = 0.f; w4p[k] = 0.f; }
+            // tiles q + 1 go to the matrix cores before tile q's results are used
+            s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, 0, lane, bfirst);
+            s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, 0, lane, blast);
 #pragma unroll
             for (int q = 0; q < D::NQ; ++q) {
+                s3_v16f t1n = t1, tnn = tn;
+                if (q + 1 < D::NQ) {
+                    t1n = mfma_tile<N, JP, OP>(s_g, 0, q + 1, lane, bfirst);
+                    tnn = mfma_tile<N, JP, OP>(s_g, 1, q + 1, lane, blast);
+                }
                 // T1 tile: (j2, j3, j4) = (4h + pi / 8, pi % 8, r % 8), pi = 2q + r / 8
-                const s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, q, lane, bfirst);
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const int pi = 2 * q + s, jl = pi >> 3, j3 = pi & 7;
@@ -220,7 +232,6 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
                     w3p[j3] = fmaf(S, bh[jl], w3p[j3]);              // w_3[j3] (this half's j2)
                 }
                 // TN tile: (j1, j2, j3) = (4h + pi / 8, pi % 8, r % 8)
-                const s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, q, lane, blast);
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const int pi = 2 * q + s, jl = pi >> 3, j2 = pi & 7;
@@ -229,6 +240,8 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
                     for (int z = 0; z < 8; ++z) P = fmaf(tn[8 * s + z], c[z], P);
                     w1l[jl] = fmaf(P, b[j2], w1l[jl]);               // w_1[j1]
                 }
+                t1 = t1n;
+                tn = tnn;
             }
             float xp = 0.f;
 #pragma unroll
@@ -264,10 +277,16 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) w3p[k] = 0.f;
             float xp = 0.f;
+            s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, 0, lane, bfirst);
+            s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, 0, lane, blast);
 #pragma unroll
             for (int q = 0; q < D::NQ; ++q) {
+                s3_v16f t1n = t1, tnn = tn;
+                if (q + 1 < D::NQ) {
+                    t1n = mfma_tile<N, JP, OP>(s_g, 0, q + 1, lane, bfirst);
+                    tnn = mfma_tile<N, JP, OP>(s_g, 1, q + 1, lane, blast);
+                }
                 // T1 tile: (j2, j3) = (8h + q, r)
-                const s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, q, lane, bfirst);
                 float S = 0.f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
@@ -277,11 +296,12 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
                 R[q] = S;
                 xp = fmaf(S, bh[q], xp);
                 // TN tile: (j1, j2) = (8h + q, r)
-                const s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, q, lane, blast);
                 float P = 0.f;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) P = fmaf(tn[r], b[r], P);
                 w1l[q] = P;                                    // w_1[j1]
+                t1 = t1n;
+                tn = tnn;
             }
             const float x = xp + __shfl_xor(xp, 32, kWave);
             float w3o[8];
@@ -311,8 +331,9 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
 // halves of 128 entries; FP32: v_mfma_f32_32x32x2f32 on quarters of 64.
 // Sums in FP32.  `buf` needs 36,864 bytes, 16-byte aligned; core receives
 // the 4,096 values (row-major j1 j2 j3 j4, the padded core layout).
+// (accumulated into acc, wavefront w's tile; ends with a barrier)
 template <int OP>
-S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__restrict__ core) {
+S3_DEV void core_grad_mx4_acc(float q, const float (&u)[4][8], float *buf, s3_v16f &acc) {
     constexpr int kPart = (OP == kOpBF16) ? 128 : 64;   // entries staged at a time
     constexpr int kRow = (OP == kOpBF16) ? 136 : 132;   // staged row: 128 values + padding
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -323,7 +344,6 @@ S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__
         pa[k] = q * u[0][k];
         pc[k] = u[2][k];
     }
-    s3_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int part = 0; part < 256 / kPart; ++part) {  // the block's 256 entries
         const int tl = tid - part * kPart;
@@ -335,8 +355,8 @@ S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__
                     uint32_t pw[4], qw[4];
 #pragma unroll
                     for (int b = 0; b < 8; b += 2) {
-                        pw[b / 2] = (uint32_t)bf16_rne(pa[a] * u[1][b]) | ((uint32_t)bf16_rne(pa[a] * u[1][b + 1]) << 16);
-                        qw[b / 2] = (uint32_t)bf16_rne(pc[a] * u[3][b]) | ((uint32_t)bf16_rne(pc[a] * u[3][b + 1]) << 16);
+                        pw[b / 2] = bf16x2(pa[a] * u[1][b], pa[a] * u[1][b + 1]);
+                        qw[b / 2] = bf16x2(pc[a] * u[3][b], pc[a] * u[3][b + 1]);
                     }
                     *(uint4 *)(row + 8 * a) = make_uint4(pw[0], pw[1], pw[2], pw[3]);
                     *(uint4 *)(row + 64 + 8 * a) = make_uint4(qw[0], qw[1], qw[2], qw[3]);
@@ -377,11 +397,24 @@ S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__
         }
         __syncthreads();
     }
+}
+
+// wavefront w's 32 x 32 tile of the 4-way core gradient, to core (4,096 values)
+S3_DEV void core_grad_mx4_store(const s3_v16f &acc, float *__restrict__ core) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int rb = wv >> 1, cb = wv & 1, i = lane & 31, kh = lane >> 5;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
         core[(size_t)(32 * rb + row) * 64 + 32 * cb + i] = acc[r];
     }
+}
+
+template <int OP>
+S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__restrict__ core) {
+    s3_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    core_grad_mx4_acc<OP>(q, u, buf, acc);
+    core_grad_mx4_store(acc, core);
 }
 
 // Core gradient of a chunk of K entries on the BF16 matrix cores (FP32
@@ -390,7 +423,7 @@ S3_DEV void core_grad_mx4(float q, const float (&u)[4][8], float *buf, float *__
 // (A[i][k] in lane i + 16 (k / 4), slot k % 4; D[4 (l / 16) + r][l % 16] in
 // lane l, register r).  Same operands and output as core_tile_mfma.
 template <int N, int JP, int K>
-S3_DEV void core_tile_mfma_bf16(const float *s_q, const float *s_u, float *core, int nthreads) {
+S3_DEV void core_tile_mfma_bf16(const float *s_q, const float *s_u, float *core, int nthreads, bool add = false) {
     constexpr int TAIL = (N == 3) ? JP * JP : JP * JP * JP;
     constexpr int NT = (TAIL + 15) / 16;
     const int NW = nthreads / kWave;
@@ -406,24 +439,28 @@ S3_DEV void core_tile_mfma_bf16(const float *s_q, const float *s_u, float *core,
         typedef float v4f __attribute__((ext_vector_type(4)));
         v4f acc = {0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < K; k0 += 16) {
-            s3_v4s a, b;
+            float av[4], bvv[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int t = k0 + 4 * kq + v;
-                const float av = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
+                av[v] = (i16 < JP) ? s_q[t * JP + i16] : 0.f;
                 float bv = s_u[(t * (N - 1)) * JP + tj[0]];
 #pragma unroll
                 for (int n = 1; n < N - 1; ++n) bv *= s_u[(t * (N - 1) + n) * JP + tj[n]];
-                a[v] = (short)bf16_rne(av);
-                b[v] = (short)bf16_rne(tv ? bv : 0.f);
+                bvv[v] = tv ? bv : 0.f;
             }
+            const s3_v4s a = bf16x4(av[0], av[1], av[2], av[3]);
+            const s3_v4s b = bf16x4(bvv[0], bvv[1], bvv[2], bvv[3]);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
         }
         if (tv) {
 #pragma unroll
             for (int r2 = 0; r2 < 4; ++r2) {
                 const int j1 = 4 * kq + r2;
-                if (j1 < JP) core[(size_t)j1 * TAIL + tau] = acc[r2];
+                if (j1 < JP) {
+                    float *c = core + (size_t)j1 * TAIL + tau;
+                    *c = add ? *c + acc[r2] : acc[r2];
+                }
             }
         }
     }

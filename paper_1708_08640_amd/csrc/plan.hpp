@@ -62,7 +62,8 @@ struct KernelSet {
     void (*core_partial)(s3_plan *, const int32_t *, int64_t, hipStream_t);
     void (*sq_err)(s3_plan *, const int32_t *, const void *, int64_t, double *, hipStream_t);
     void (*predict)(s3_plan *, const int32_t *, int64_t, void *, const void *, hipStream_t);  // Gp: padded core
-    void (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t, hipEvent_t, hipEvent_t);
+    // returns the number of tensor workgroups (partial tables) it launched
+    int64_t (*lf_tensor)(s3_plan *, int64_t, int64_t, double, hipStream_t, hipEvent_t, hipEvent_t);
     void (*mx_format)(s3_plan *, hipStream_t);  // matrix-core sets: core operands from Gp into mx_g
     int det_chunk;  // tensor entries per det block and core chunk
 };
@@ -189,21 +190,23 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
         hipLaunchKernelGGL((k_predict<N, JP, T, CT>), dim3(grid_for(nnz, 256, 1ll << 30)), dim3(256), 0, st, a,
                            (const T *)Gp, (T *)out);
     }
-    static void lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st, hipEvent_t e0,
-                          hipEvent_t e1) {
+    static int64_t lf_tensor(s3_plan *p, int64_t first, int64_t count, double eta, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1) {
         if (p->exact)
-            lockfree_tensor_launch<N, JP, T, true, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+            return lockfree_tensor_launch<N, JP, T, true, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
                                                           (const T *)p->Gp, first, count, (T)eta, st, e0, e1,
                                                           p->mx_g);
         else
-            lockfree_tensor_launch<N, JP, T, false, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
+            return lockfree_tensor_launch<N, JP, T, false, CT>(p->lf, tensor_args<T>(p, p->b.x_idx, p->b.x_val, p->nX),
                                                            (const T *)p->Gp, first, count, (T)eta, st, e0, e1,
                                                            p->mx_g);
     }
     static void mx_format(s3_plan *p, hipStream_t st) {
         if constexpr (is_mx(CT) && mfma_shape<N, JP>() && std::is_same<T, float>::value) {
             constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
-            hipLaunchKernelGGL((k_mx_format<N, JP, OP>), dim3(1), dim3(256), 0, st, (const float *)p->Gp, p->mx_g);
+            constexpr int n = 2 * MfmaDims<N, JP>::NQ * kWave * MfmaOp<OP, JP>::NC * MfmaOp<OP, JP>::V;
+            hipLaunchKernelGGL((k_mx_format<N, JP, OP>), dim3((n + 255) / 256), dim3(256), 0, st, (const float *)p->Gp,
+                               p->mx_g);
         }
     }
 };

@@ -885,7 +885,7 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
         HIPCHK(p, hipEventRecord(p->ev0, st));
         s3_status s;
         p->pev_used = 0;
-        auto round = [&](int64_t f, int64_t c, double e, hipStream_t s_) {
+        auto round = [&](int64_t f, int64_t c, double e, hipStream_t s_) -> int64_t {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (p->prof && c > 0) {
                 e0 = prof_event(p, p->pev_used);
@@ -894,7 +894,7 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
                 else e0 = e1 = nullptr;
             }
             p->ks.mx_format(p, s_);  // the core as the last round left it
-            p->ks.lf_tensor(p, f, c, e, s_, e0, e1);
+            return p->ks.lf_tensor(p, f, c, e, s_, e0, e1);
         };
         if (p->tsize == 8) {
             pad_core<double>(p, st);
