@@ -1,15 +1,15 @@
 """The CP special case (hyper-diagonal core, Section 3's S^3CMTF-CP) on the
 GPU against the oracle's CP mode: det batches and epochs, loss / RMSE /
-predictions, the adjoint, and lock-free RMSE against sequential SGD.  Same
-tolerances as the Tucker tests: FP64 1e-10, FP32 1e-5 per batch (2e-4 after
-a whole epoch)."""
+predictions, the adjoint, and lock-free RMSE against the oracle.  Same
+checks as the Tucker tests: each batch's update from a re-synced start, row
+by row, FP64 1e-10 and FP32 1e-5, also for every batch of a whole epoch."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from synth import item_order
-from tests.gpu_util import compare_params, rel, setup
+from tests.gpu_util import UNIT, check_batches, compare_params, rel, setup
 
 pytestmark = pytest.mark.gpu
 
@@ -27,17 +27,20 @@ CASES = [
 def test_cp_det_batches_match_oracle(name, dtype, batch, over):
     print(f"\n[cp-det] {name} {dtype} batch={batch}", flush=True)
     cfg, p, plan, ref, order = setup(name, dtype, batch, True, core="cp", **over)
+    check_batches(p, plan, order, batch, 0.01, range(min(3, plan.n_batches())), True, TOL[dtype], UNIT[dtype],
+                  "cp", cp=True)
+    cfg, p, plan, ref, order = setup(name, dtype, batch, True, core="cp", **over)
     for b in range(min(3, plan.n_batches())):
         plan.det_batches(b, 1, 0.01)
         oracle.minibatch_epoch(ref, p, order, batch, 0.01, b, 1, damping=True)
-        compare_params(plan, ref, TOL[dtype], f"batch {b}")
+    compare_params(plan, ref, TOL[dtype], "lockstep")
 
 
 def test_cp_det_epoch_matches_oracle():
     cfg, p, plan, ref, order = setup("cfg2_slice", "f32", 4096, True, core="cp")
-    plan.epoch(0, "det")
-    oracle.minibatch_epoch(ref, p, order, 4096, oracle.eta_at(cfg.eta0, cfg.mu, 0), damping=True)
-    compare_params(plan, ref, 2e-4, "after 1 epoch")
+    w = check_batches(p, plan, order, 4096, oracle.eta_at(cfg.eta0, cfg.mu, 0), range(plan.n_batches()), True,
+                      TOL["f32"], UNIT["f32"], "cp epoch", cp=True)
+    print(f"{plan.n_batches()} batches, worst error / bound {w:.3f}", flush=True)
 
 
 @pytest.mark.parametrize("name,dtype", [("cfg1", "f64"), ("cfg5_slice", "f32")])
@@ -71,16 +74,30 @@ def test_cp_backward_matches_oracle_adjoint(name, dtype, batch):
         assert rel(a.cpu().numpy(), b) <= tol
 
 
-def test_cp_lockfree_tracks_sequential_sgd():
-    cfg, p, plan, ref, order = setup("cfg2_slice", "f32", 4096, True, round_items=4096, core="cp")
-    want, got = [], []
-    for ep in range(3):
-        oracle.sgd_epoch(ref, p, item_order(p.n_items, 7, ep), oracle.eta_at(cfg.eta0, cfg.mu, ep))
-        want.append(oracle.rmse(ref, p.test_idx, p.test_val))
-        plan.epoch(ep, "lockfree")
+def test_cp_lockfree_tracks_oracle():
+    """As the Tucker lock-free tests: after 20 epochs the mean over two tile
+    seeds within 1 % of the damped det mini-batch oracle with batch = the
+    round size, each seed within 2 %."""
+    import os
+    threads = max(1, min(16, os.cpu_count() or 1))
+    cfg, p, plan, ref, order = setup("cfg2_slice", "f32", 4096, True, round_items=4096, core="cp", order_seed=7)
+    det = ref.copy()
+    fixed = item_order(p.n_items, 7, 0)
+    for ep in range(20):
+        oracle.minibatch_epoch(det, p, fixed, 4096, oracle.eta_at(cfg.eta0, cfg.mu, ep), damping=True,
+                               threads=threads)
+    want = oracle.rmse(det, p.test_idx, p.test_val)
+    got = []
+    for seed in (7, 8):
+        if seed != 7:
+            cfg, p, plan, _, _ = setup("cfg2_slice", "f32", 4096, True, round_items=4096, core="cp",
+                                       order_seed=seed)
+        for ep in range(20):
+            plan.epoch(ep, "lockfree")
         got.append(plan.rmse())
-    print("[cp-lockfree] oracle", want, "gpu", got, flush=True)
-    assert np.isfinite(got[-1]) and abs(got[-1] - want[-1]) <= 0.05 * want[-1]
+        print(f"[cp-lockfree] seed {seed}: {got[-1]:.4f} vs det oracle {want:.4f}", flush=True)
+        assert np.isfinite(got[-1]) and abs(got[-1] - want) <= 0.02 * want
+    assert abs(np.mean(got) - want) <= 0.01 * want
 
 
 def test_cp_orthogonalize_is_rejected():

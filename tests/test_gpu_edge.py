@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from synth.gen import MatrixSpec
-from tests.gpu_util import compare_params, setup
+from tests.gpu_util import UNIT, check_batches, compare_params, setup
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +30,10 @@ def test_edge_det_matches_oracle(what, name, batch, over, core):
     cfg, p, plan, ref, order = setup(name, "f64", batch, True, core=core, **over)
     if what.startswith("whole tiles"):
         assert p.n_train % 256 == 0
-    for b in range(min(3, plan.n_batches())):
-        plan.det_batches(b, 1, 0.01)
-        oracle.minibatch_epoch(ref, p, order, batch, 0.01, b, 1, damping=True)
-        compare_params(plan, ref, 1e-10, f"{what}, batch {b}")
+    check_batches(p, plan, order, batch, 0.01, range(min(3, plan.n_batches())), True, 1e-10, UNIT["f64"], what,
+                  cp=(core == "cp"))
+    U, G, V = plan.params_numpy()
+    ref = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices], cp=(core == "cp"))
     f, _, _ = plan.loss()
     assert abs(f - oracle.loss(ref, p)[0]) <= 1e-10 * abs(f)
 

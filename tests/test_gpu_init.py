@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import compare_params, setup
+from tests.gpu_util import UNIT, check_batches, setup
 
 pytestmark = pytest.mark.gpu
 
@@ -90,9 +90,4 @@ def test_init_params_moments_and_determinism():
 def test_det_batch_from_device_init_matches_oracle():
     cfg, p, plan, ref, order = setup("cfg1", "f64", 500, True)
     plan.init_params(99, 0.1)
-    U, G, V = plan.params_numpy()
-    ref = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices])
-    for b in range(2):
-        plan.det_batches(b, 1, 0.01)
-        oracle.minibatch_epoch(ref, p, order, 500, 0.01, b, 1, damping=True)
-        compare_params(plan, ref, 1e-10, f"batch {b}")
+    check_batches(p, plan, order, 500, 0.01, range(2), True, 1e-10, UNIT["f64"], "device init")

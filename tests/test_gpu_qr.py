@@ -3,13 +3,13 @@ oracle's Householder QR.  Q is unique up to the sign of each column, so the
 oracle's columns (and the matching core slices and V columns) are flipped to
 agree with the GPU's before comparing; the GPU's R has a positive diagonal.
 Also: the GPU's factors have orthonormal columns and every prediction is
-unchanged.  Tolerances: FP64 1e-10; FP32 1e-5 normwise (FP32 storage of the
-results, Gram and Cholesky in FP64)."""
+unchanged.  Tolerances: FP64 1e-10; FP32 1e-5, normwise and for every row
+(FP32 storage of the results, Gram and Cholesky in FP64)."""
 import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import rel, setup
+from tests.gpu_util import _row_rel, rel, setup
 
 pytestmark = pytest.mark.gpu
 
@@ -50,11 +50,13 @@ def test_orthogonalize_matches_oracle(name, dtype):
     tol = TOL[dtype]
     for n in range(len(gU)):
         assert rel(gU[n], want.U[n]) <= tol, f"Q[{n}] rel {rel(gU[n], want.U[n]):.2e}"
+        assert _row_rel(gU[n], want.U[n]) <= tol, f"Q[{n}] worst row {_row_rel(gU[n], want.U[n]):.2e}"
         qtq = gU[n].T @ gU[n]
         assert np.abs(qtq - np.eye(qtq.shape[0])).max() <= tol, f"Q[{n}]^T Q[{n}] != I"
     assert rel(gG, want.G) <= tol, f"G rel {rel(gG, want.G):.2e}"
     for m in range(len(gV)):
         assert rel(gV[m], want.V[m]) <= tol, f"V[{m}] rel {rel(gV[m], want.V[m]):.2e}"
+        assert _row_rel(gV[m], want.V[m]) <= tol, f"V[{m}] worst row {_row_rel(gV[m], want.V[m]):.2e}"
     x1 = plan.predict(p.test_idx).cpu().numpy().astype(np.float64)
     assert rel(x1, x0) <= tol
     for m in range(len(cfg.matrices)):
