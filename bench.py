@@ -2,10 +2,19 @@
 """Benchmark: tensor + coupled-matrix nonzero updates per second per epoch, at
 a fixed held-out RMSE, on one MI355X.
 
-Workload (default): the 3-way 1M x 100K x 100 tensor with 10M Zipf(1.2)
-entries (9M train / 1M held out), Tucker core 10x10x10, one coupled 1M x 1M
-matrix with 5M entries on mode 1; FP32; lock-free mode.  One "step" is one
-epoch: every training tensor entry and every matrix entry updated once.
+Workload (default, the largest configuration): the 4-way 1M x 500K x 1000 x
+24 tensor with 200M Zipf(1.2) entries (180M train / 20M held out), Tucker
+core 8^4, three coupled matrices (1M x 1M with 30M entries, 500K x 300 with
+20M, a dense 1000 x 50); lock-free mode; the dense part of the contraction on
+the matrix cores with BF16 operands, FP32 master parameters.  One "step" is
+one epoch: every training tensor entry and every matrix entry updated once.
+The 10M-entry 3-way workload (FP32, vector-unit contraction) is measured
+after it and reported as secondary keys.
+
+Fixed held-out RMSE: after the timed epochs the parameters are reset to
+their initial values and E* epochs are run again; the held-out RMSE after
+epoch E* must be at most 1.01 times the FP64 oracle's sequential SGD
+(Algorithm 1, one worker) at E* (tests/golden/).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -15,12 +24,17 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tensor+matrix nonzero updates/sec per epoch at fixed held-out RMSE, 1 GPU"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+E_STAR = {"cfg2": 3, "cfg5": 3}
 
 
 def log(msg):
@@ -47,16 +61,17 @@ def matrix_entry_flops(rank):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp"):
+    for f in ("common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "mfma.hpp", "plan.hpp"):
         with open(os.path.join(ROOT, "paper_1708_08640_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the kernel sources changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_lf_tensor_cfg2_hbm_traffic.md")
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary, or None when there is none or the kernel sources changed
+    since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -65,22 +80,70 @@ def profiled_traffic(kernel):
             if ":" in line and not line.startswith(("#", " ", "|")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("source_sha256_16") != kernel_source_hash() or kernel not in fields.get("kernel", ""):
+    if fields.get("source_sha256_16") != kernel_source_hash() or fields.get("kernel", "") != kernel:
         return None
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(cfg, p, U, G, V, sample, seed):
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(cfg, p, U, G, V, sample, seed, batch):
+    """The FP64 oracle on the host cores, on the first `sample` items of an
+    item order of the same workload: the deterministic mini-batch epoch
+    evaluated by one thread per core (the value), and sequential SGD on one
+    core (Algorithm 1 with one worker, reported beside it)."""
     import oracle
     from synth import item_order
-    params = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices])
+    nproc, model = cpu_info()
+    threads = min(nproc, 16)
     order = item_order(p.n_items, seed, 0)[:sample]
+    params = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices])
     t = time.perf_counter()
-    oracle.sgd_epoch(params, p, order, cfg.eta0)
-    dt = time.perf_counter() - t
-    return {"value": sample / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"sequential FP64 SGD (Algorithm 1, one worker) over the first {sample:,} items of an "
-                      f"epoch order of the same workload ({dt:.1f} s)"}
+    oracle.minibatch_epoch(params, p, order, min(batch, sample), cfg.eta0, damping=True, threads=threads)
+    dt_det = time.perf_counter() - t
+    n_seq = max(1, sample // 8)
+    params = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices])
+    t = time.perf_counter()
+    oracle.sgd_epoch(params, p, order[:n_seq], cfg.eta0)
+    dt_seq = time.perf_counter() - t
+    return {"value": sample / dt_det, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 det mini-batch oracle (damped, batches of {min(batch, sample):,}, {threads} threads, "
+                      f"bitwise the one-thread result) over the first {sample:,} items of an epoch order of the "
+                      f"same workload ({dt_det:.1f} s); host: {nproc} logical CPUs, {model}",
+            "sequential_sgd_value": n_seq / dt_seq,
+            "sequential_sgd_sample": f"sequential FP64 SGD (Algorithm 1, one worker, 1 core) over the first "
+                                     f"{n_seq:,} of those items ({dt_seq:.1f} s)",
+            "nproc": nproc, "cpu_model": model}
+
+
+def oracle_target(config, epoch):
+    """1.01 x the mean over item orders of the stored sequential-SGD oracle
+    RMSE after `epoch` epochs, and the det oracle's (round size) beside it."""
+    import glob
+    sgd, det = [], []
+    for f in glob.glob(os.path.join(ROOT, "tests", "golden", f"{config}_sgd_s*.json")):
+        with open(f) as fh:
+            r = json.load(fh)["rmse"]
+        if len(r) >= epoch and all(np.isfinite(r[:epoch])):
+            sgd.append(r[epoch - 1])
+    for f in glob.glob(os.path.join(ROOT, "tests", "golden", f"{config}_det524288_s*.json")):
+        with open(f) as fh:
+            r = json.load(fh)["rmse"]
+        if len(r) >= epoch:
+            det.append(r[epoch - 1])
+    return (1.01 * float(np.mean(sgd)) if sgd else None, float(np.mean(sgd)) if sgd else None,
+            float(np.mean(det)) if det else None)
 
 
 def scaling_sweep(args):
@@ -123,28 +186,177 @@ def scaling_sweep(args):
         torch.cuda.empty_cache()
 
 
+def mx_entry_work(ranks):
+    """Algorithmic work of one tensor entry in the matrix-core contraction:
+    the two mode products G x_1 u^(1) and G x_N u^(N) (2 J^N flops each) and
+    the entry's share of the core gradient (2 J^N) on the matrix cores; on
+    the vector units the contractions of the two products' outputs with the
+    remaining rows (about 3 J^(N-1) multiply-adds, 6 J^(N-1) flops) and the
+    gradients, curvatures and updates (10 flops per row element)."""
+    K = 1
+    for j in ranks:
+        K *= j
+    tail = K // ranks[0]
+    return 6 * K, 6 * tail + 10 * sum(ranks)
+
+
+def generate(args, config):
+    from synth import get_config, init_params, make_problem
+    cfg = get_config(config)
+    if args.scale != 1.0:
+        import dataclasses
+        mats = tuple(m if m.nnz == cfg.dims[m.mode] * m.cols else dataclasses.replace(m, nnz=int(m.nnz * args.scale))
+                     for m in cfg.matrices)
+        cfg = cfg.scaled(name=f"{cfg.name}_x{args.scale:g}", nnz=int(cfg.nnz * args.scale), matrices=mats,
+                         description=cfg.description + f"; entry counts x {args.scale:g} (profiling)")
+    log(f"generating {cfg.name}: {cfg.description}")
+    p = make_problem(cfg)
+    U, G, V = init_params(cfg)
+    if args.core == "cp":  # the hyper-diagonal part of the same seeded core
+        G = np.array([G[(r,) * cfg.order] for r in range(cfg.ranks[0])])
+    log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {p.n_items - p.n_train:,} matrix entries")
+    return cfg, p, U, G, V
+
+
+def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
+    import torch
+    from paper_1708_08640_amd import S3Plan
+    from synth import item_order
+    cfg, p, U, G, V = data
+    n_updates = p.n_items
+    order = item_order(p.n_items, args.seed, 0) if mode == "det" else None
+    plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=args.batch, order=order, damping=True,
+                               round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows,
+                               contraction=contraction, core=args.core)
+    torch.cuda.synchronize()
+    rmse0 = plan.rmse()
+    log(f"bound; initial held-out RMSE {rmse0:.4f}")
+    for e in range(warmup):
+        plan.epoch(e, mode)
+        torch.cuda.synchronize()
+        log(f"warmup epoch {e}: RMSE {plan.rmse():.4f}")
+
+    plan.set_profiling(True)
+    kernel_ms, launches, epoch_ms = 0.0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(warmup, warmup + steps):
+        te = time.perf_counter()
+        plan.epoch(e, mode)
+        ms, n = plan.last_epoch_profile()  # waits for the epoch
+        kernel_ms += ms
+        launches += n
+        epoch_ms.append((time.perf_counter() - te) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_profiling(False)
+    E = warmup + steps
+    rmse = plan.rmse()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    log(f"timed {steps} epochs: {ms_per_step:.3f} ms/epoch; RMSE after {E} epochs {rmse:.4f}")
+
+    # fixed held-out RMSE: E* epochs again from the initial parameters
+    estar = E_STAR.get(config, 3)
+    with torch.no_grad():
+        for dst, src in zip(plan.U + [plan.G] + plan.V, U + [G] + V):
+            dst.copy_(torch.as_tensor(np.asarray(src), dtype=dst.dtype))
+    traj = []
+    for e in range(estar):
+        plan.epoch(e, mode)
+        traj.append(plan.rmse())
+    target, sgd_mean, det_mean = oracle_target(config, estar) if args.scale == 1.0 else (None, None, None)
+    log(f"quality pass: RMSE after epochs 1..{estar}: {' '.join(f'{v:.4f}' for v in traj)}; target "
+        f"{target if target is None else round(target, 4)}")
+
+    # roofline of the dominant kernel (the round kernel, or the det entries kernel)
+    mat_flops = sum(matrix_entry_flops(cfg.ranks[s.mode]) * len(p.mat_val[m]) for m, s in enumerate(cfg.matrices))
+    secs = kernel_ms / 1e3
+    kname = ("k_lf_tensor_mx" if contraction == "matrix" else "k_lf_tensor") if mode == "lockfree" else "k_det_entries"
+    default_shape = (args.scale == 1.0 and args.core == "tucker" and args.round_items == 524288
+                     and args.hot_rows == 64 and mode == "lockfree")
+    traffic = profiled_traffic(kname, f"{config}_{dtype}") if default_shape else None
+    if contraction == "matrix":
+        # at the two peaks the vector-unit share of the work takes longer than
+        # the matrix-core share, so the vector units set the roof
+        mx, valu = mx_entry_work(cfg.ranks)
+        peak = PEAK_BF16_MFMA_TFLOPS if dtype == "bf16" else PEAK_FP32_MFMA_TFLOPS
+        mx_flops = mx * p.n_train * steps
+        valu_flops = (valu * p.n_train + mat_flops) * steps
+        mx_t = mx_flops / secs / 1e12 if secs > 0 else None
+        valu_t = valu_flops / secs / 1e12 if secs > 0 else None
+        roof_s = mx_flops / (peak * 1e12) + valu_flops / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
+        roofline = {"bound": "alu", "kernel": kname, "achieved": valu_t, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                    "unit": "TFLOP/s", "frac": (valu_t / PEAK_FP32_VECTOR_TFLOPS) if valu_t else None,
+                    "traffic": traffic, "valu_flops_per_tensor_entry": valu,
+                    "mfma": {"achieved": mx_t, "peak": peak, "unit": "TFLOP/s",
+                             "frac": (mx_t / peak) if mx_t else None, "flops_per_tensor_entry": mx,
+                             "dtype": dtype},
+                    "time_at_roof_fraction": roof_s / secs if secs > 0 else None}
+    else:
+        flops = (tensor_entry_flops(cfg.ranks) * p.n_train + mat_flops) * steps
+        achieved = flops / secs / 1e12 if secs > 0 else None
+        roofline = {"bound": "alu", "kernel": kname,
+                    "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                    "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
+                    "traffic": traffic,
+                    "flops_per_tensor_entry": tensor_entry_flops(cfg.ranks)}
+    roofline.update({"launches": launches, "avg_launch_ms": kernel_ms / max(launches, 1),
+                     "kernel_share_of_epoch": kernel_ms / (t1 - t0) / 1e3,
+                     "flops_per_matrix_entry": matrix_entry_flops(cfg.ranks[cfg.matrices[0].mode]) if cfg.matrices
+                     else None})
+    if args.core == "cp":
+        # CP: O(NJ) flops per entry, so the bound is HBM: algorithmic bytes =
+        # index + value stream and every touched row read and written once
+        J = cfg.ranks[0]
+        t_bytes = 4 * cfg.order + 4 + 2 * 4 * J * cfg.order
+        m_bytes = 12 + 2 * 2 * 4 * J
+        nbytes = (t_bytes * p.n_train + m_bytes * (n_updates - p.n_train)) * steps
+        gbs = nbytes / secs / 1e9 if secs > 0 else None
+        roofline.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": (gbs / PEAK_HBM_GBS) if gbs else None, "traffic": None,
+                         "bytes_per_tensor_entry": t_bytes, "bytes_per_matrix_entry": m_bytes})
+    out = {"cfg": cfg, "ms_per_step": ms_per_step, "value": n_updates / (ms_per_step / 1e3),
+           "updates_per_epoch": n_updates, "heldout_rmse": rmse, "heldout_rmse_init": rmse0, "rmse_epochs": E,
+           "epoch_ms": epoch_ms, "roofline": roofline, "rmse_estar": estar, "rmse_trajectory": traj,
+           "rmse_target": target, "rmse_ok": (traj[-1] <= target) if target is not None else None,
+           "oracle_sgd_rmse": sgd_mean, "oracle_det_rmse": det_mean}
+    del plan
+    torch.cuda.empty_cache()
+    if cpu:
+        log(f"timing the FP64 oracle on {args.cpu_sample:,} items (CPU baseline)")
+        out["cpu"] = cpu_baseline(cfg, p, U, G, V, args.cpu_sample, args.seed, args.batch)
+        log(f"oracle: {out['cpu']['value']:.0f} updates/s ({out['cpu']['cores']} threads), sequential "
+            f"{out['cpu']['sequential_sgd_value']:.0f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2, help="timed epochs")
     ap.add_argument("--warmup", type=int, default=1, help="untimed epochs before the timed ones")
-    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--config", default="cfg5")
     ap.add_argument("--mode", default="lockfree", choices=["lockfree", "det"])
     ap.add_argument("--round-items", type=int, default=524288)
     ap.add_argument("--hot-rows", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--core", default="tucker", choices=["tucker", "cp"],
                     help="cp: the hyper-diagonal core (the CP special case), measured against the HBM roof")
-    ap.add_argument("--contraction", default="reuse", choices=["reuse", "naive", "matrix"],
-                    help="naive: the per-entry contraction without reuse of partial products (ablation); "
-                         "matrix: the dense part on the matrix cores")
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16"],
-                    help="bf16: FP32 master parameters, BF16 operands on the matrix cores (needs --contraction "
-                         "matrix)")
+    ap.add_argument("--contraction", default=None, choices=["reuse", "naive", "matrix"],
+                    help="reuse: the single pass on the vector units; naive: without reuse of partial products "
+                         "(ablation); matrix: the dense part on the matrix cores (default where it is built)")
+    ap.add_argument("--dtype", default=None, choices=["f32", "bf16"],
+                    help="bf16: FP32 master parameters, BF16 operands on the matrix cores (default with the "
+                         "matrix contraction)")
+    ap.add_argument("--no-f32-compare", action="store_true",
+                    help="skip the FP32-operand run of the same workload that follows a BF16 headline")
+    ap.add_argument("--no-det-compare", action="store_true",
+                    help="skip the det mini-batch run of the same workload that follows a lock-free headline")
+    ap.add_argument("--secondary", default="cfg2", help="second workload reported as extra keys ('' for none)")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="profiling runs only: entry counts of the tensor and of the sparse matrices times this "
                          "(same dimensions, ranks and rounds)")
-    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--scaling", choices=["dims", "nnz"], default=None,
@@ -161,7 +373,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -175,125 +386,75 @@ def main():
         print(json.dumps({"copy_bytes": n * 4, "copies": 3}), flush=True)
         return
 
-    from paper_1708_08640_amd import S3Plan
-    from synth import get_config, init_params, item_order, make_problem
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.scaling:
         scaling_sweep(args)
         return
-    cfg = get_config(args.config)
-    if args.scale != 1.0:
-        import dataclasses
-        mats = tuple(m if m.nnz == cfg.dims[m.mode] * m.cols else dataclasses.replace(m, nnz=int(m.nnz * args.scale))
-                     for m in cfg.matrices)
-        cfg = cfg.scaled(name=f"{cfg.name}_x{args.scale:g}", nnz=int(cfg.nnz * args.scale), matrices=mats,
-                         description=cfg.description + f"; entry counts x {args.scale:g} (profiling)")
-    log(f"generating {cfg.name}: {cfg.description}")
-    p = make_problem(cfg)
-    U, G, V = init_params(cfg)
-    if args.core == "cp":  # the hyper-diagonal part of the same seeded core
-        G = np.array([G[(r,) * cfg.order] for r in range(cfg.ranks[0])])
-    n_updates = p.n_items
-    log(f"{p.n_train:,} train entries, {p.test_val.shape[0]:,} held out, {n_updates - p.n_train:,} matrix entries")
-    order = item_order(p.n_items, args.seed, 0) if args.mode == "det" else None
-    plan = S3Plan.from_problem(p, (U, G, V), dtype=args.dtype, batch=args.batch, order=order, damping=True,
-                               round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows,
-                               contraction=args.contraction, core=args.core)
-    torch.cuda.synchronize()
-    rmse0 = plan.rmse()
-    log(f"bound; initial held-out RMSE {rmse0:.4f}")
 
-    for e in range(args.warmup):
-        plan.epoch(e, args.mode)
-        torch.cuda.synchronize()
-        log(f"warmup epoch {e}: RMSE {plan.rmse():.4f}")
+    def defaults(config):
+        from synth import get_config
+        c = get_config(config)
+        jp = max(c.ranks)
+        built = (c.order == 4 and 5 <= jp <= 8) or (c.order == 3 and 13 <= jp <= 16)
+        ct = args.contraction or ("matrix" if (built and args.core == "tucker") else "reuse")
+        dt = args.dtype or ("bf16" if ct == "matrix" else "f32")
+        return ct, dt
 
-    plan.set_profiling(True)
-    kernel_ms, launches, epoch_ms = 0.0, 0, []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e in range(args.warmup, args.warmup + args.steps):
-        te = time.perf_counter()
-        plan.epoch(e, args.mode)
-        ms, n = plan.last_epoch_profile()  # waits for the epoch
-        kernel_ms += ms
-        launches += n
-        epoch_ms.append((time.perf_counter() - te) * 1e3)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.set_profiling(False)
-    rmse = plan.rmse()
-    E = args.warmup + args.steps
-    log(f"timed {args.steps} epochs: {(t1 - t0) * 1e3 / args.steps:.3f} ms/epoch; RMSE after {E} epochs {rmse:.4f}")
-
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = n_updates / (ms_per_step / 1e3)
-
-    # held-out RMSE target from the oracle's trajectory (sequential FP64 SGD)
-    target = None
-    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle_rmse.json")
-    if os.path.exists(gold):
-        with open(gold) as f:
-            g = json.load(f)
-        if len(g["rmse"]) >= E:
-            target = 1.01 * g["rmse"][E - 1]
-
-    mat_flops = sum(matrix_entry_flops(cfg.ranks[s.mode]) * len(p.mat_val[m]) for m, s in enumerate(cfg.matrices))
-    # the timed launch (lock-free: k_lf_tensor; det: k_det_entries) also runs
-    # the matrix entries
-    flops = (tensor_entry_flops(cfg.ranks) * p.n_train + mat_flops) * args.steps
-    achieved = flops / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else None
-    roofline = {
-        "bound": "alu", "kernel": "k_lf_tensor" if args.mode == "lockfree" else "k_det_entries",
-        "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
-        # counters were taken for the default launch only (lock-free, reuse
-        # contraction, Tucker core, 10M-entry workload, rounds of 524,288
-        # items, 64 hot rows)
-        "traffic": profiled_traffic("k_lf_tensor") if (args.mode == "lockfree" and cfg.name == "cfg2_zipf_10m"
-                                                       and args.contraction == "reuse" and args.core == "tucker"
-                                                       and args.round_items == 524288 and args.hot_rows == 64)
-        else None,
-        "flops_per_tensor_entry": tensor_entry_flops(cfg.ranks),
-        "flops_per_matrix_entry": matrix_entry_flops(cfg.ranks[cfg.matrices[0].mode]) if cfg.matrices else None,
-        "launches": launches,
-        "avg_launch_ms": kernel_ms / max(launches, 1), "kernel_share_of_epoch": kernel_ms / (t1 - t0) / 1e3,
-    }
-
-    if args.core == "cp":
-        # CP: O(NJ) flops per entry, so the bound is HBM: algorithmic bytes =
-        # index + value stream and every touched row read and written once
-        J = cfg.ranks[0]
-        t_bytes = 4 * cfg.order + 4 + 2 * 4 * J * cfg.order
-        m_bytes = 12 + 2 * 2 * 4 * J
-        nbytes = (t_bytes * p.n_train + m_bytes * (n_updates - p.n_train)) * args.steps
-        gbs = nbytes / (kernel_ms / 1e3) / 1e9 if kernel_ms > 0 else None
-        roofline.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": (gbs / PEAK_HBM_GBS) if gbs else None, "traffic": None,
-                         "bytes_per_tensor_entry": t_bytes, "bytes_per_matrix_entry": m_bytes})
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"timing the FP64 oracle on {args.cpu_sample:,} items (CPU baseline)")
-        cpu = cpu_baseline(cfg, p, U, G, V, args.cpu_sample, args.seed)
-        log(f"oracle: {cpu['value']:.0f} updates/s")
-
+    ct, dt = defaults(args.config)
+    data = generate(args, args.config)
+    head = run(args, data, args.config, ct, dt, args.mode, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+    cfg = head["cfg"]
+    extra = {}
+    if dt == "bf16" and not args.no_f32_compare:
+        # the same workload, plan settings and tile seed with FP32 operands
+        f = run(args, data, args.config, ct, "f32", args.mode, args.steps, args.warmup)
+        extra["fp32_same_gpu"] = {
+            "dtype": "f32", "contraction": ct, "value": f["value"], "unit": "updates/s",
+            "ms_per_step": f["ms_per_step"], "heldout_rmse": f["heldout_rmse"], "rmse_epochs": f["rmse_epochs"],
+            "rmse_trajectory": f["rmse_trajectory"], "rmse_ok": f["rmse_ok"],
+            "bf16_speedup": head["value"] / f["value"],
+            "bf16_minus_fp32_final_rmse": head["rmse_trajectory"][-1] - f["rmse_trajectory"][-1],
+            "roofline": f["roofline"]}
+    if args.mode == "lockfree" and not args.no_det_compare:
+        # the deterministic mini-batch mode on the same workload and operands
+        d = run(args, data, args.config, ct, dt, "det", args.steps, args.warmup)
+        extra["det_mode"] = {
+            "dtype": dt, "contraction": ct, "batch": args.batch, "damping": "curvature", "value": d["value"],
+            "unit": "updates/s", "ms_per_step": d["ms_per_step"], "heldout_rmse": d["heldout_rmse"],
+            "rmse_epochs": d["rmse_epochs"], "rmse_trajectory": d["rmse_trajectory"], "rmse_ok": d["rmse_ok"],
+            "roofline": d["roofline"]}
+    del data
+    if args.secondary and args.secondary != args.config:
+        sct, sdt = defaults(args.secondary)
+        sec = run(args, generate(args, args.secondary), args.secondary, sct, sdt, args.mode, args.steps,
+                  args.warmup)
+        extra["secondary"] = {
+            "workload": f"{sec['cfg'].name}: {sec['cfg'].description}", "contraction": sct, "dtype": sdt,
+            "value": sec["value"], "unit": "updates/s", "ms_per_step": sec["ms_per_step"],
+            "heldout_rmse": sec["heldout_rmse"], "rmse_epochs": sec["rmse_epochs"],
+            "rmse_estar": sec["rmse_estar"], "rmse_trajectory": sec["rmse_trajectory"],
+            "rmse_target": sec["rmse_target"], "rmse_ok": sec["rmse_ok"],
+            "oracle_sgd_rmse": sec["oracle_sgd_rmse"], "oracle_det_rmse": sec["oracle_det_rmse"],
+            "roofline": sec["roofline"]}
     out = {
-        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "metric": METRIC, "value": head["value"], "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.description}", "mode": args.mode,
                    "round_items": args.round_items if args.mode == "lockfree" else None,
                    "hot_rows": args.hot_rows if args.mode == "lockfree" else None,
                    "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
-                   "contraction": args.contraction, "core": args.core,
-                   "updates_per_epoch": n_updates, "parallelism": "single GPU"},
-        "heldout_rmse": rmse, "heldout_rmse_init": rmse0, "rmse_epochs": E, "rmse_target": target,
-        "rmse_ok": (rmse <= target) if target is not None else None,
-        "epoch_ms": epoch_ms,
-        "roofline": roofline, "cpu_baseline": cpu,
+                   "contraction": ct, "core": args.core, "master_dtype": "f32",
+                   "updates_per_epoch": head["updates_per_epoch"], "parallelism": "single GPU"},
+        "heldout_rmse": head["heldout_rmse"], "heldout_rmse_init": head["heldout_rmse_init"],
+        "rmse_epochs": head["rmse_epochs"], "rmse_estar": head["rmse_estar"],
+        "rmse_trajectory": head["rmse_trajectory"], "rmse_target": head["rmse_target"],
+        "rmse_ok": head["rmse_ok"], "oracle_sgd_rmse": head["oracle_sgd_rmse"],
+        "oracle_det_rmse": head["oracle_det_rmse"], "epoch_ms": head["epoch_ms"],
+        "roofline": head["roofline"], "cpu_baseline": head.get("cpu"),
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

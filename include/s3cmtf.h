@@ -229,8 +229,13 @@ s3_status s3_loss(s3_plan *plan, double *out, void *stream);
  * Synchronous; S3_ERR_NONFINITE if not finite.                           */
 s3_status s3_rmse(s3_plan *plan, double *out, void *stream);
 
-/* Forward of the prediction map: x~ for nnz entries idx (device, SoA) into
- * xhat (device, compute type).  Asynchronous.                             */
+/* Forward of the prediction map, the Tucker reconstruction of Eq (4):
+ * x~ = sum over core positions j of g_j * prod_n u^(n)_{i_n, j_n}, for nnz
+ * entries idx (device, SoA: idx[n * nnz + e] is entry e's mode-n index) into
+ * xhat (device, nnz values in the compute type: FP64 plans FP64, FP32 and
+ * BF16-operand plans FP32).  The caller owns both buffers.  The indices are
+ * checked against their modes first (S3_ERR_INDEX_RANGE, nothing written),
+ * which synchronises `stream`; the prediction itself is enqueued on it.    */
 s3_status s3_predict(s3_plan *plan, const int32_t *idx, int64_t nnz, void *xhat,
                      void *stream);
 

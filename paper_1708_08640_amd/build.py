@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libs3cmtf.so")
 SOURCES = ["s3cmtf.hip", "sets_f32_3.hip", "sets_f32_4.hip", "sets_f64.hip", "sets_cp.hip",
            "sets_naive.hip", "sets_mx.hip"]
-HEADERS = ["common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "mfma.hpp", "qr.hpp", "plan.hpp"]
+HEADERS = ["common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "mfma.hpp", "qr.hpp", "plan.hpp", "sort.hpp"]
 ARCH = os.environ.get("S3_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -21,13 +21,12 @@
 // All reductions have a fixed order, so a det-mode run is bitwise
 // reproducible.
 #pragma once
-#include <hipcub/hipcub.hpp>
-
 #include <cstdint>
 
 #include "common.hpp"
 #include "contract.hpp"
 #include "mfma.hpp"
+#include "sort.hpp"
 
 namespace s3 {
 
@@ -57,40 +56,6 @@ static __global__ void k_check_range(const int32_t *__restrict__ idx, int64_t n,
         bad |= (v < 0) | ((int64_t)v >= limit);
     }
     if (bad) atomicOr(flag, 1);
-}
-
-// Row counts.  Power-law indices make plain per-entry atomics serialise on
-// the head rows, so each workgroup sorts a chunk of kHistItems x 256 indices
-// in LDS and adds one count per run of equal indices in a lane's items.
-constexpr int kHistItems = 16;
-
-static __global__ __launch_bounds__(256) void k_hist(const int32_t *__restrict__ idx, int64_t n,
-                                              int32_t *__restrict__ cnt) {
-    using Sort = hipcub::BlockRadixSort<int32_t, 256, kHistItems>;
-    __shared__ typename Sort::TempStorage tmp;
-    constexpr int64_t kChunkItems = 256 * kHistItems;
-    for (int64_t base = (int64_t)blockIdx.x * kChunkItems; base < n; base += (int64_t)gridDim.x * kChunkItems) {
-        int32_t k[kHistItems];
-#pragma unroll
-        for (int i = 0; i < kHistItems; ++i) {
-            const int64_t e = base + (int64_t)i * 256 + threadIdx.x;  // coalesced
-            k[i] = (e < n) ? idx[e] : INT32_MAX;
-        }
-        __syncthreads();  // the previous chunk's sort storage is free
-        Sort(tmp).Sort(k);  // lane t now holds ranks 16 t .. 16 t + 15
-        int32_t cur = k[0], run = 1;
-#pragma unroll
-        for (int i = 1; i < kHistItems; ++i) {
-            if (k[i] == cur) {
-                ++run;
-            } else {
-                if (cur != INT32_MAX) atomicAdd(&cnt[cur], run);
-                cur = k[i];
-                run = 1;
-            }
-        }
-        if (cur != INT32_MAX) atomicAdd(&cnt[cur], run);
-    }
 }
 
 // key = batch * (M + 1) + type (0 tensor, m + 1 matrix m); value = item id
@@ -127,9 +92,10 @@ __global__ void k_bounds(const K *__restrict__ key, int64_t n, int64_t nkeys,
 
 // Contributions of every sorted item position to one parameter group.
 // Group g < N: rows of U^(g) (tensor entries, and entries of matrices
-// coupled to mode g).  Group N + m: rows of V_m.  key = (batch << 32) | row,
-// val = gradient offset | (curvature offset << 32) into the batch scratch.
-// Positions that do not touch the group get key ~0 and sort last.
+// coupled to mode g).  Group N + m: rows of V_m.  key = (batch << rbits) |
+// row, val = gradient offset | (curvature offset << 32) into the batch
+// scratch.  Positions that do not touch the group get key nb << rbits, above
+// every real key, and sort last.
 struct GroupArgs {
     const int32_t *sorted_ids;   // item ids grouped by (batch, type)
     const uint32_t *sorted_keys; // their (batch, type) keys
@@ -151,6 +117,8 @@ struct GroupArgs {
     int64_t m_base[kMaxM]; // start of each matrix's scratch region
     int64_t m_stride[kMaxM];
     int32_t m_J[kMaxM];
+    int32_t rbits;         // bits of a row index in the sort key
+    int64_t nb;            // batches; key nb << rbits marks "no contribution"
 };
 
 static __global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_out,
@@ -163,13 +131,13 @@ static __global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_o
         const int type = (int)(k % (a.M + 1));
         const int64_t slot = p - a.type_off[k];
         const int64_t id = a.sorted_ids[p];
-        uint64_t kk = ~0ull, vv = 0;
+        uint64_t kk = (uint64_t)a.nb << a.rbits, vv = 0;
         if (type == 0) {
             if (a.group < a.N) {
                 const int64_t row = a.x_idx[(int64_t)a.group * a.x_nnz + id];
                 const int64_t go = slot * a.t_stride + a.t_goff;
                 const int64_t co = slot * a.t_stride + a.t_coff;
-                kk = ((uint64_t)b << 32) | (uint64_t)row;
+                kk = ((uint64_t)b << a.rbits) | (uint64_t)row;
                 vv = (uint64_t)go | ((uint64_t)co << 32);
             }
         } else {
@@ -178,10 +146,10 @@ static __global__ void k_group_contrib(GroupArgs a, uint64_t *__restrict__ key_o
             const int64_t base = a.m_base[m] + slot * a.m_stride[m];
             const int J = a.m_J[m];
             if (a.group == a.mat_mode[m]) {
-                kk = ((uint64_t)b << 32) | (uint64_t)a.y_row[m][e];
+                kk = ((uint64_t)b << a.rbits) | (uint64_t)a.y_row[m][e];
                 vv = (uint64_t)base | ((uint64_t)(base + 2 * J) << 32);
             } else if (a.group == a.N + m) {
-                kk = ((uint64_t)b << 32) | (uint64_t)a.y_col[m][e];
+                kk = ((uint64_t)b << a.rbits) | (uint64_t)a.y_col[m][e];
                 vv = (uint64_t)(base + J) | ((uint64_t)(base + 2 * J + 1) << 32);
             }
         }
@@ -200,15 +168,15 @@ static __global__ void k_seg_flags(const uint64_t *__restrict__ key, int64_t n, 
 static __global__ void k_seg_write(const uint64_t *__restrict__ key, const int32_t *__restrict__ flag,
                             const int32_t *__restrict__ seg_id, int64_t n,
                             int64_t *__restrict__ seg_start, int32_t *__restrict__ seg_row,
-                            uint32_t *__restrict__ seg_batch) {
+                            uint32_t *__restrict__ seg_batch, int rbits) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; p < n; p += stride) {
         if (flag[p]) {
             const int64_t s = seg_id[p] - 1;
             seg_start[s] = p;
-            seg_row[s] = (int32_t)(key[p] & 0xffffffffull);
-            seg_batch[s] = (uint32_t)(key[p] >> 32);
+            seg_row[s] = (int32_t)(key[p] & ((1ull << rbits) - 1ull));
+            seg_batch[s] = (uint32_t)(key[p] >> rbits);
         }
         if (p == n - 1) seg_start[seg_id[p]] = n;
     }

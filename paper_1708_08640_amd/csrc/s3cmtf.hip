@@ -4,7 +4,6 @@
 // out of one caller-provided workspace (bump allocation, 256-byte aligned).
 #include "s3cmtf.h"
 
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -238,6 +237,21 @@ void det_batch(s3_plan *p, int64_t b, double eta, const void *gx, const void *co
 template <typename T> size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz,
                                     const int64_t *y_nnz, bool with_order, size_t *temp_bytes_out);
 
+// The det-mode build packs each contribution's per-batch scratch offsets into
+// 32-bit halves and sorts items by a 32-bit (batch, type) key: both must fit.
+bool det_fits_32bit(const s3_plan *p, int64_t x_nnz, const int64_t *y_nnz) {
+    const int N = p->N, M = p->M;
+    const int64_t B = p->d.batch;
+    int64_t n_items = x_nnz;
+    for (int m = 0; m < M; ++m) n_items += y_nnz[m];
+    const int64_t nb = (n_items + B - 1) / B;
+    int64_t end = std::min(B, x_nnz) * ((int64_t)N * p->JP + N + 2);  // as the per-batch scratch carve
+    for (int m = 0; m < M; ++m)
+        end += std::min(B, std::max<int64_t>(y_nnz[m], 1)) * (2 * (int64_t)p->d.rank[p->d.mat_mode[m]] + 2);
+    const int64_t lim = (int64_t)1 << 32;
+    return end < lim && nb * (M + 1) <= lim;
+}
+
 }  // namespace
 
 // ------------------------------------------------ allocation-free prediction
@@ -372,6 +386,9 @@ s3_status s3_workspace_size(const s3_plan *cp, int64_t x_nnz, int64_t t_nnz, con
     if (!p || !bytes || x_nnz < 1 || t_nnz < 0 || (p->M > 0 && !y_nnz)) return S3_ERR_INVALID_ARG;
     for (int m = 0; m < p->M; ++m)
         if (y_nnz[m] < 0) return S3_ERR_INVALID_ARG;
+    if (!det_fits_32bit(p, x_nnz, y_nnz))
+        return fail(p, S3_ERR_UNSUPPORTED, "det batches of %lld items: per-batch scratch offsets or batch keys "
+                    "exceed 32 bits", (long long)p->d.batch);
     size_t temp = 0;
     *bytes = (p->tsize == 8) ? layout<double>(p, nullptr, x_nnz, t_nnz, y_nnz, true, &temp)
                              : layout<float>(p, nullptr, x_nnz, t_nnz, y_nnz, true, &temp);
@@ -409,13 +426,7 @@ void carve_det_temps(Carver &c, DetTemps &t, int64_t n, int64_t nb, int M) {
     t.segid = c.take<int32_t>((size_t)n);
     t.segb = c.take<uint32_t>((size_t)n);
     t.boff = c.take<int64_t>((size_t)nb + 1);
-    size_t s1 = 0, s2 = 0, s3b = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, s1, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                             (int32_t *)nullptr, (int32_t *)nullptr, (int)n);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, s2, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (uint64_t *)nullptr, (uint64_t *)nullptr, (int)n);
-    (void)hipcub::DeviceScan::InclusiveSum(nullptr, s3b, (int32_t *)nullptr, (int32_t *)nullptr, (int)n);
-    t.temp_bytes = std::max({s1, s2, s3b});
+    t.temp_bytes = std::max(sort_temp_bytes(n), sizeof(int32_t) * scan_temp_elems(n));
     t.temp = c.take<char>(t.temp_bytes + 256);
 }
 
@@ -509,7 +520,6 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
     int32_t *flags = t.flags, *segid = t.segid;
     uint32_t *segb = t.segb;
     int64_t *boff = t.boff;
-    size_t tb = t.temp_bytes;
     void *temp = t.temp;
 
     int64_t mat_end[S3_MAX_MATRICES] = {};
@@ -518,10 +528,8 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
     HIPCHK(p, hipMemcpyAsync(d_mat_end, mat_end, sizeof(int64_t) * S3_MAX_MATRICES, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, p->b.order, n, B, p->nX,
                        (int32_t)M, (const int64_t *)d_mat_end, key_in, ids_in);
-    const int nkey_bits = 32;
-    HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(temp, tb, key_in, key_out, ids_in, p->sorted_ids, (int)n, 0,
-                                                 nkey_bits, st));
     const int64_t nkeys = nb * (M + 1);
+    HIPCHK(p, radix_sort_pairs(key_in, ids_in, key_out, p->sorted_ids, n, bits_for((uint64_t)nkeys), temp, st));
     hipLaunchKernelGGL(k_bounds<uint32_t>, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, st, key_out, n,
                        nkeys, type_off);
     {
@@ -560,6 +568,7 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
     ga.x_idx = p->b.x_idx;
     ga.x_nnz = p->nX;
     ga.t_stride = p->t_stride;
+    ga.nb = nb;
     for (int m = 0; m < M; ++m) {
         ga.y_row[m] = p->b.y_row[m];
         ga.y_col[m] = p->b.y_col[m];
@@ -583,8 +592,10 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
             G.J = p->d.rank[p->d.mat_mode[g - N]];
             G.rows = p->d.mat_cols[g - N];
         }
+        ga.rbits = bits_for((uint64_t)G.rows);
         hipLaunchKernelGGL(k_group_contrib, dim3(grid_for(n, 256, 16384)), dim3(256), 0, st, ga, gk_in, gv_in);
-        HIPCHK(p, hipcub::DeviceRadixSort::SortPairs(temp, tb, gk_in, gk_out, gv_in, gv_out, (int)n, 0, 64, st));
+        HIPCHK(p, radix_sort_pairs(gk_in, gv_in, gk_out, gv_out, n, ga.rbits + bits_for((uint64_t)nb + 1), temp,
+                                   st));
         const int64_t nv = G.n_valid;
         G.h_boff.assign((size_t)nb + 1, 0);
         G.h_moff.assign((size_t)nb + 1, 0);
@@ -593,9 +604,9 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
         if (nv == 0) { G.nseg = 0; continue; }
         HIPCHK(p, hipMemcpyAsync(G.contrib, gv_out, sizeof(uint64_t) * nv, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_seg_flags, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, st, gk_out, nv, flags);
-        HIPCHK(p, hipcub::DeviceScan::InclusiveSum(temp, tb, flags, segid, (int)nv, st));
+        HIPCHK(p, scan_i32(flags, segid, nv, false, (int32_t *)temp, st));
         hipLaunchKernelGGL(k_seg_write, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, st, gk_out, flags, segid,
-                           nv, G.seg_start, G.seg_row, segb);
+                           nv, G.seg_start, G.seg_row, segb, ga.rbits);
         int32_t nseg32 = 0;
         HIPCHK(p, hipMemcpyAsync(&nseg32, segid + nv - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(p, hipStreamSynchronize(st));
@@ -614,7 +625,7 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
                         int64_t *count) -> s3_status {
             hipLaunchKernelGGL(k_seg_class, dim3(grid_for(G.nseg, 256, 16384)), dim3(256), 0, st, G.seg_start,
                                G.nseg, lo, hi, flags);
-            HIPCHK(p, hipcub::DeviceScan::InclusiveSum(temp, tb, flags, segid, (int)G.nseg, st));
+            HIPCHK(p, scan_i32(flags, segid, G.nseg, false, (int32_t *)temp, st));
             int32_t n32 = 0;
             HIPCHK(p, hipMemcpyAsync(&n32, segid + G.nseg - 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             HIPCHK(p, hipStreamSynchronize(st));
@@ -664,6 +675,9 @@ template <typename T> s3_status bind_impl(s3_plan *p, const s3_buffers *buf, voi
     int64_t y_nnz[S3_MAX_MATRICES] = {};
     for (int m = 0; m < M; ++m) y_nnz[m] = buf->y_nnz[m];
     const bool with_order = buf->order != nullptr;
+    if (with_order && !det_fits_32bit(p, buf->x_nnz, y_nnz))
+        return fail(p, S3_ERR_UNSUPPORTED, "det batches of %lld items: per-batch scratch offsets or batch keys "
+                    "exceed 32 bits", (long long)p->d.batch);
     size_t temp_bytes = 0;
     const size_t need = layout<T>(p, nullptr, buf->x_nnz, buf->t_nnz, y_nnz, with_order, &temp_bytes);
     if (!ws || ws_bytes < need)
@@ -713,14 +727,11 @@ template <typename T> s3_status bind_impl(s3_plan *p, const s3_buffers *buf, voi
     // counts |Omega_X^{n,i}| and |Omega_Y^{2,k}|
     for (int n = 0; n < N; ++n) {
         HIPCHK(p, hipMemsetAsync(p->cnt[n], 0, sizeof(int32_t) * p->d.dims[n], st));
-        hipLaunchKernelGGL(k_hist, dim3(grid_for(p->nX, 256, 4096)), dim3(256), 0, st,
-                           buf->x_idx + (int64_t)n * p->nX, p->nX, p->cnt[n]);
+        row_counts(buf->x_idx + (int64_t)n * p->nX, p->nX, p->d.dims[n], p->cnt[n], st);
     }
     for (int m = 0; m < M; ++m) {
         HIPCHK(p, hipMemsetAsync(p->cntV[m], 0, sizeof(int32_t) * p->d.mat_cols[m], st));
-        if (y_nnz[m] > 0)
-            hipLaunchKernelGGL(k_hist, dim3(grid_for(y_nnz[m], 256, 4096)), dim3(256), 0, st, buf->y_col[m],
-                               y_nnz[m], p->cntV[m]);
+        row_counts(buf->y_col[m], y_nnz[m], p->d.mat_cols[m], p->cntV[m], st);
     }
     p->det_ready = false;
     if (with_order) {

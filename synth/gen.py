@@ -415,7 +415,7 @@ def _cfg4():
     return _cfg3().scaled(
         name="cfg4_bf16_100m", ranks=(16, 16, 16), nnz=100_000_000,
         seed_data=31, seed_split=32, seed_init=33, dtype="bf16",
-        description="as cfg3 with core 16^3 and 100M tensor nnz (specified with BF16 storage; run in FP32)",
+        description="as cfg3 with core 16^3 and 100M tensor nnz (BF16 matrix-core operands, FP32 masters)",
     )
 
 
@@ -428,7 +428,7 @@ def _cfg5():
                   MatrixSpec(mode=1, cols=300, nnz=20_000_000, col_law=1.2, value_law=U01),
                   MatrixSpec(mode=2, cols=50, nnz=50_000, col_law="uniform", value_law=U01)),
         eta0=0.01, lambda_reg=0.01, seed_data=41, seed_split=42, seed_init=43, dtype="bf16",
-        description="4-way 1Mx500Kx1000x24, 200M nnz Zipf(1.2), core 8^4, three coupled matrices (specified with BF16 storage; run in FP32)",
+        description="4-way 1Mx500Kx1000x24, 200M nnz Zipf(1.2), core 8^4, three coupled matrices (BF16 matrix-core operands, FP32 masters)",
     )
 
 
@@ -465,9 +465,15 @@ def _cfg5_slice():
                   MatrixSpec(mode=2, cols=50, nnz=50_000, col_law="uniform", value_law=U01)))
 
 
+def _cfg2_planted():
+    return _cfg2().scaled(name="cfg2_planted_10m", planted=True,
+                          description="as cfg2 with planted values: clip(round(3 + per-index offsets + noise), 1, 5)")
+
+
 CONFIGS = {
     "cfg1": _cfg1,
     "cfg2": _cfg2,
+    "cfg2_planted": _cfg2_planted,
     "cfg3": _cfg3,
     "cfg4": _cfg4,
     "cfg5": _cfg5,

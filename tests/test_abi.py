@@ -44,7 +44,7 @@ def _desc(_abi, **kw):
     d.dtype, d.eta0, d.mu, d.lambda_reg, d.lambda_m = 1, 0.01, 0.1, 0.01, 10.0
     d.batch, d.round_items = 64, 64
     for k, v in kw.items():
-        if k in ("dims", "rank"):
+        if k in ("dims", "rank", "mat_mode", "mat_cols"):
             for n, x in enumerate(v):
                 getattr(d, k)[n] = x
         else:
@@ -137,3 +137,42 @@ def test_bind_rejects_small_workspace():
         assert b"workspace" in buf.value
     finally:
         lib.s3_plan_destroy(h)
+
+
+def test_det_offsets_beyond_32_bits_are_rejected():
+    """The det build packs per-batch scratch offsets and (batch, type) sort
+    keys into 32 bits; sizes that overflow them are refused up front."""
+    _abi, lib = _lib()
+    y = (C.c_int64 * 3)(0, 0, 0)
+    sz = C.c_size_t()
+    buf = C.create_string_buffer(256)
+    cases = [
+        # batch x (3 x 16 + 5) scratch elements: 50M fits, 100M does not
+        (dict(rank=(16, 16, 16), batch=50_000_000), 50_000_000, 0),
+        (dict(rank=(16, 16, 16), batch=100_000_000), 100_000_000, -3),
+        # 2^31 - 1 single-item batches x (3 matrices + 1) keys
+        (dict(batch=1, n_mat=3, mat_mode=(0, 1, 2), mat_cols=(50, 50, 50)), 2**31 - 1, -3),
+        (dict(batch=2, n_mat=3, mat_mode=(0, 1, 2), mat_cols=(50, 50, 50)), 2**31 - 1, 0),
+    ]
+    for kw, x_nnz, status in cases:
+        d = _desc(_abi, **kw)
+        h = C.c_void_p()
+        assert lib.s3_plan_create(C.byref(d), C.byref(h)) == 0
+        try:
+            assert lib.s3_workspace_size(h, x_nnz, 0, y, C.byref(sz)) == status, kw
+            if status:
+                lib.s3_last_error(h, buf, 256)
+                assert b"32 bits" in buf.value
+                # bind with an item order refuses the same sizes before touching memory
+                b = _abi.S3Buffers()
+                fake = 0x10000
+                b.x_idx, b.x_val, b.x_nnz = fake, fake, x_nnz
+                for n in range(3):
+                    b.U[n] = fake
+                b.G = fake
+                for m in range(d.n_mat):
+                    b.V[m] = fake
+                b.order = fake
+                assert lib.s3_bind(h, C.byref(b), C.c_void_p(fake), 1 << 40, None) == -3
+        finally:
+            lib.s3_plan_destroy(h)

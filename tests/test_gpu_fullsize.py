@@ -12,9 +12,16 @@ the launch configurations the benchmark times.
   exported parameters entry by entry.
 * Lock-free mode, rounds of 524,288 items and 64 hot rows: racy by design, so
   checked through properties that hold at any size -- rows no training entry
-  touches stay bitwise unchanged, everything stays finite, and the held-out
-  RMSE after three epochs is within 1 % of sequential FP64 SGD's (the stored
-  oracle trajectory, Section 4 of the paper measures accuracy the same way).
+  touches stay bitwise unchanged, everything stays finite -- and through the
+  held-out RMSE against the stored FP64 oracle trajectories
+  (tests/golden/, written by make_oracle_rmse.py): after 3 epochs below
+  1.01 times sequential SGD's (Algorithm 1, one worker; mean of five item
+  orders), the benchmark's fixed-RMSE target; after 25 epochs, over three
+  tile-shuffle seeds, the mean within 1 % of the damped det mini-batch
+  oracle's at the round size (each seed within 2 %) and below 1.01 times
+  sequential SGD's.
+* The planted variant (values with a learnable signal) at the same size:
+  after 10 lock-free epochs within 1 % of the det oracle's held-out RMSE.
 """
 import json
 import os
@@ -111,6 +118,19 @@ def test_predictions_full_size(full):
     assert r <= 1e-5
 
 
+def _gold(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)["rmse"]
+
+
+def _mean_at(names, epoch):
+    return float(np.mean([_gold(n)[epoch - 1] for n in names]))
+
+
+SGD = [f"cfg2_sgd_s{s}.json" for s in (7, 8, 10, 11, 12)]
+DET = [f"cfg2_det524288_s{s}.json" for s in (7, 8)]
+
+
 def test_lockfree_full_size_properties(full):
     cfg, p, params = full
     U0 = params[0]
@@ -130,11 +150,9 @@ def test_lockfree_full_size_properties(full):
         assert np.all(np.isfinite(gU[n])), f"U[{n}] not finite"
         assert np.array_equal(gU[n][~seen[n]], U0[n][~seen[n]]), f"unobserved rows of U[{n}] changed"
     assert np.all(np.isfinite(gG)) and all(np.all(np.isfinite(v)) for v in gV)
-    with open(os.path.join(HERE, "golden", "cfg2_oracle_rmse.json")) as f:
-        gold = json.load(f)
-    target = 1.01 * gold["rmse"][2]
+    target = 1.01 * _mean_at(SGD, 3)
     assert rmse[0] < plan_init_rmse(p, params) and rmse[2] < rmse[0]
-    assert rmse[2] <= target, f"epoch-3 RMSE {rmse[2]:.4f} > 1.01 x oracle {gold['rmse'][2]:.4f}"
+    assert rmse[2] <= target, f"epoch-3 RMSE {rmse[2]:.4f} > 1.01 x sequential SGD {target / 1.01:.4f}"
 
 
 def plan_init_rmse(p, params):
@@ -142,20 +160,47 @@ def plan_init_rmse(p, params):
                        p.test_idx, p.test_val)
 
 
-def test_lockfree_full_size_rmse_over_seeds(full):
-    """The tile shuffle seed changes every round's composition: three seeds
-    all reach the 1 % target after three epochs."""
+def test_lockfree_full_size_tracks_oracle(full):
+    """25 epochs, three tile-shuffle seeds, against the stored oracles."""
     cfg, p, params = full
-    with open(os.path.join(HERE, "golden", "cfg2_oracle_rmse.json")) as f:
-        target = 1.01 * json.load(f)["rmse"][2]
     from paper_1708_08640_amd import S3Plan
     got = []
     for seed in (7, 8, 9):
         plan = S3Plan.from_problem(p, params, dtype="f32", damping=True, seed=seed, round_items=ROUND,
                                    hot_rows=HOT, batch=BATCH, order=None)
-        for e in range(3):
+        for e in range(25):
             plan.epoch(e, "lockfree")
         got.append(plan.rmse())
         del plan
-    print(f"[fullsize] lock-free RMSE after 3 epochs, seeds 7/8/9: {got} (target {target:.4f})", flush=True)
-    assert max(got) <= target
+    det, sgd = _mean_at(DET, 25), _mean_at(SGD, 25)
+    print(f"[fullsize] lock-free RMSE after 25 epochs, seeds 7/8/9: {got}; det oracle {det:.4f}, "
+          f"sequential SGD {sgd:.4f}", flush=True)
+    assert all(abs(g - det) <= 0.02 * det for g in got)
+    assert abs(float(np.mean(got)) - det) <= 0.01 * det
+    assert max(got) <= 1.01 * sgd
+
+
+def test_lockfree_planted_full_size():
+    """The planted variant: a held-out RMSE with real signal to learn."""
+    print("\n[fullsize] generating the planted 10M-entry workload", flush=True)
+    cfg = get_config("cfg2_planted")
+    p = rounded_problem(make_problem(cfg), "f32")
+    r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+    U, G, V = init_params(cfg)
+    params = ([r(u) for u in U], r(G), [r(v) for v in V])
+    det = _gold("cfg2_planted_det524288_s7.json")
+    got = []
+    for seed in (7, 8):
+        plan = _plan(p, params, order=None) if seed == SEED else None
+        if plan is None:
+            from paper_1708_08640_amd import S3Plan
+            plan = S3Plan.from_problem(p, params, dtype="f32", damping=True, seed=seed, round_items=ROUND,
+                                       hot_rows=HOT, batch=BATCH, order=None)
+        for e in range(len(det)):
+            plan.epoch(e, "lockfree")
+        got.append(plan.rmse())
+        del plan
+    print(f"[fullsize] planted: lock-free RMSE after {len(det)} epochs {got}, det oracle {det[-1]:.4f} "
+          f"(untrained {plan_init_rmse(p, params):.4f})", flush=True)
+    assert all(abs(g - det[-1]) <= 0.02 * det[-1] for g in got)
+    assert abs(float(np.mean(got)) - det[-1]) <= 0.01 * det[-1]
