@@ -352,7 +352,7 @@ def main():
                     help="skip the FP32-operand run of the same workload that follows a BF16 headline")
     ap.add_argument("--no-det-compare", action="store_true",
                     help="skip the det mini-batch run of the same workload that follows a lock-free headline")
-    ap.add_argument("--secondary", default="cfg2", help="second workload reported as extra keys ('' for none)")
+    ap.add_argument("--secondary", default="cfg2", help="second workload reported as extra keys ('none' for none)")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="profiling runs only: entry counts of the tensor and of the sparse matrices times this "
                          "(same dimensions, ranks and rounds)")
@@ -425,7 +425,7 @@ def main():
             "rmse_epochs": d["rmse_epochs"], "rmse_trajectory": d["rmse_trajectory"], "rmse_ok": d["rmse_ok"],
             "roofline": d["roofline"]}
     del data
-    if args.secondary and args.secondary != args.config:
+    if args.secondary not in ("", "none") and args.secondary != args.config:
         sct, sdt = defaults(args.secondary)
         sec = run(args, generate(args, args.secondary), args.secondary, sct, sdt, args.mode, args.steps,
                   args.warmup)
