@@ -187,17 +187,23 @@ def scaling_sweep(args):
 
 
 def mx_entry_work(ranks):
-    """Algorithmic work of one tensor entry in the matrix-core contraction:
-    the two mode products G x_1 u^(1) and G x_N u^(N) (2 J^N flops each) and
-    the entry's share of the core gradient (2 J^N) on the matrix cores; on
-    the vector units the contractions of the two products' outputs with the
-    remaining rows (about 3 J^(N-1) multiply-adds, 6 J^(N-1) flops) and the
-    gradients, curvatures and updates (10 flops per row element)."""
+    """Algorithmic work of one tensor entry in the matrix-core contraction,
+    as (matrix-core flops, VALU flops).  Matrix cores: the two dense products
+    (2 J^N multiply-adds each) and the entry's share of the core gradient
+    (J^N), 6 J^N flops in all.  VALU, 4-way: the two Khatri-Rao columns
+    (J1 J2 + J3 J4 products), the four leave-one-out contractions of the
+    products' outputs (2 (J1 J2 + J3 J4) multiply-adds) and x~ (J4); 3-way:
+    the contractions of the two mode products' tails (3 J2 J3 multiply-adds).
+    Both: 10 flops per row element for gradients, curvatures and updates."""
     K = 1
     for j in ranks:
         K *= j
-    tail = K // ranks[0]
-    return 6 * K, 6 * tail + 10 * sum(ranks)
+    if len(ranks) == 4:
+        kr = ranks[0] * ranks[1] + ranks[2] * ranks[3]
+        valu = kr + 4 * kr + 2 * ranks[3]
+    else:
+        valu = 6 * (K // ranks[0])
+    return 6 * K, valu + 10 * sum(ranks)
 
 
 def generate(args, config):
@@ -276,22 +282,26 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
                      and args.hot_rows == 64 and mode == "lockfree")
     traffic = profiled_traffic(kname, f"{config}_{dtype}") if default_shape else None
     if contraction == "matrix":
-        # at the two peaks the vector-unit share of the work takes longer than
-        # the matrix-core share, so the vector units set the roof
+        # the bound is whichever share takes longer at its peak: the
+        # matrix-core flops (BF16 or FP32 rate) or the VALU flops
         mx, valu = mx_entry_work(cfg.ranks)
         peak = PEAK_BF16_MFMA_TFLOPS if dtype == "bf16" else PEAK_FP32_MFMA_TFLOPS
         mx_flops = mx * p.n_train * steps
         valu_flops = (valu * p.n_train + mat_flops) * steps
         mx_t = mx_flops / secs / 1e12 if secs > 0 else None
         valu_t = valu_flops / secs / 1e12 if secs > 0 else None
-        roof_s = mx_flops / (peak * 1e12) + valu_flops / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
-        roofline = {"bound": "alu", "kernel": kname, "achieved": valu_t, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                    "unit": "TFLOP/s", "frac": (valu_t / PEAK_FP32_VECTOR_TFLOPS) if valu_t else None,
-                    "traffic": traffic, "valu_flops_per_tensor_entry": valu,
-                    "mfma": {"achieved": mx_t, "peak": peak, "unit": "TFLOP/s",
-                             "frac": (mx_t / peak) if mx_t else None, "flops_per_tensor_entry": mx,
-                             "dtype": dtype},
-                    "time_at_roof_fraction": roof_s / secs if secs > 0 else None}
+        mx_roof = mx_flops / (peak * 1e12)
+        valu_roof = valu_flops / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
+        mfma = {"achieved": mx_t, "peak": peak, "unit": "TFLOP/s", "frac": (mx_t / peak) if mx_t else None,
+                "flops_per_tensor_entry": mx, "dtype": dtype}
+        valu_d = {"achieved": valu_t, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                  "frac": (valu_t / PEAK_FP32_VECTOR_TFLOPS) if valu_t else None, "flops_per_tensor_entry": valu}
+        main_, other, bound = (mfma, valu_d, "mfma") if mx_roof >= valu_roof else (valu_d, mfma, "alu")
+        roofline = {"bound": bound, "kernel": kname, "achieved": main_["achieved"], "peak": main_["peak"],
+                    "unit": "TFLOP/s", "frac": main_["frac"], "traffic": traffic,
+                    "flops_per_tensor_entry": main_["flops_per_tensor_entry"],
+                    ("valu" if bound == "mfma" else "mfma"): other,
+                    "time_at_roof_fraction": (mx_roof + valu_roof) / secs if secs > 0 else None}
     else:
         flops = (tensor_entry_flops(cfg.ranks) * p.n_train + mat_flops) * steps
         achieved = flops / secs / 1e12 if secs > 0 else None

@@ -467,6 +467,31 @@ __global__ __launch_bounds__(kTile, (lf_min_waves<N, JP, CT>())) void k_lf_tenso
 // the blocks after the tensor ones) are those of k_lf_tensor.  The core
 // gradient runs on the FP32 or BF16 matrix cores, summed in FP32.  FP32
 // parameters (the master copies).
+// One lane's entry stream of a tensor tile in a round (see k_lf_tensor_mx)
+template <int N, typename T> struct LfStream {
+    int32_t idx[N];
+    T reg[N];
+    T xv;
+    uint2 ms;
+};
+
+template <int N, typename T>
+S3_DEV void lf_fetch_stream(const TensorArgs<T> &A, const LFArgs<T> &L, int64_t it, LfStream<N, T> &s, int64_t &e,
+                            bool &live) {
+    const int64_t tile = lf_perm(L.tile_base + it, L.pa, L.pb, L.n_tiles);
+    e = tile * kTile + threadIdx.x;
+    live = e < A.nnz;
+    if (live) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            s.idx[n] = A.idx[(int64_t)n * A.nnz + e];
+            s.reg[n] = L.meta_reg[(int64_t)n * A.nnz + e];
+        }
+        s.xv = A.val[e];
+        s.ms = L.meta_slot[e];
+    }
+}
+
 template <int N, int JP, bool EXACT, int CT>
 __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, const void *__restrict__ g_fmt,
                                                            LFArgs<float> L, LFMatArgs<float> Y, int64_t n_tensor,
@@ -506,23 +531,31 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
     T lg_tot = T(0), cnt_tot = T(0);  // thread 0: curvature and entry counts of its tiles
     bool first = true;
 
+    // A tile's entry streams (mode indices, value, hot positions,
+    // regularisers) are loaded while the tile before it is processed, so at a
+    // tile's start only its row gathers wait on memory.
+    LfStream<N, T> cs;
+    int64_t e = 0;
+    bool live = false;
+    lf_fetch_stream<N, T>(A, L, blockIdx.x, cs, e, live);
+
 #pragma unroll 1
     for (int64_t it = blockIdx.x; it < n_tiles; it += n_tensor) {  // uniform over the block
         const int64_t tile = lf_perm(L.tile_base + it, L.pa, L.pb, L.n_tiles);
-        const int64_t e = tile * kTile + tid;
-        const bool live = e < A.nnz;
         T u[N][JP];
         int32_t rows[N];
-        if (live) {
-            load_rows<N, JP, T, EXACT>(A, e, u, rows);
-        } else {
 #pragma unroll
-            for (int n = 0; n < N; ++n) {
-                rows[n] = 0;
+        for (int n = 0; n < N; ++n) {
+            rows[n] = live ? cs.idx[n] : 0;
+            const T *r = A.U[n] + (int64_t)rows[n] * (EXACT ? JP : A.J[n]);
 #pragma unroll
-                for (int k = 0; k < JP; ++k) u[n][k] = T(0);
-            }
+            for (int k = 0; k < JP; ++k) u[n][k] = (live && (EXACT || k < A.J[n])) ? r[k] : T(0);
         }
+        const bool more = it + n_tensor < n_tiles;
+        LfStream<N, T> ns;
+        int64_t ne = 0;
+        bool nlive = false;
+        if (more) lf_fetch_stream<N, T>(A, L, it + n_tensor, ns, ne, nlive);
         // the wavefront's entry slots: rows in, x~ and w_n out
         T *slots = s_stage + (size_t)wv * kWave * SLOT;
         T *mine = slots + (size_t)lane * SLOT;
@@ -549,13 +582,12 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
         __syncthreads();  // the slots are reused for the hot-row staging below
         T q = T(0), LG = T(0);
         if (live) {
-            const T xv = A.val[e];
-            const uint2 ms = L.meta_slot[e];
-            q = -(xv - xhat);
+            const uint2 ms = cs.ms;
+            q = -(cs.xv - xhat);
             LG = T(1);
 #pragma unroll
             for (int n = 0; n < N; ++n) {
-                const T reg = L.meta_reg[(int64_t)n * A.nnz + e];
+                const T reg = cs.reg[n];
                 T ww = T(0), uu = T(0);
 #pragma unroll
                 for (int k = 0; k < JP; ++k) {
@@ -616,6 +648,11 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
             __syncthreads();
         }
         first = false;
+        if (more) {
+            cs = ns;
+            e = ne;
+            live = nlive;
+        }
     }
     if constexpr (N == 4) core_grad_mx4_store(cacc, core);
     if (tid == 0) {

@@ -1,29 +1,34 @@
 // Dense part of the per-entry contraction on the matrix cores.
 //
-// For 64 entries (one per lane of a wavefront) whose factor rows are staged
-// in LDS, two mode products of the core (Eq 4's contraction taken one mode
-// at a time, Definition 1):
-//   T1_e = G x_1 u^(1)_e     (a tensor over modes 2..N)
-//   TN_e = G x_N u^(N)_e     (a tensor over modes 1..N-1)
-// are (tail x JP) . (JP x 32 entries) products on the matrix cores: the core,
-// matricised with the other modes as rows, is the A operand (staged in LDS in
-// the instruction's lane order) and the 32 entries' rows of the contracted
-// mode are B.  An output column (one entry) lands in lanes j and j + 32, each
-// with half of the tail.  The rest runs on the VALU in those two lanes:
-//   from T1: x~ and w_2 .. w_N (T1 is contracted with the remaining rows and
-//            every partial contraction is reused, as in Algorithm 3),
-//   from TN: w_1 = TN contracted with u^(2) .. u^(N-1).
-// The tail order of each lane half is chosen so that every leave-one-out
-// vector except two is complete inside a lane; those two and x~ are summed
-// with the partner lane (lane ^ 32).  Cost per entry: 4 J^N multiply-adds on
-// the matrix cores (instead of 2 J^N on the VALU) and about 3 J^(N-1) on
-// the VALU.
+// A wavefront contracts 64 entries (one per lane) whose factor rows are
+// staged in LDS, 32 at a time.  The dense products are (rows x depth) .
+// (depth x 32 entries) products on the matrix cores: the core, matricised,
+// is the A operand (staged in LDS in the instruction's lane order), and the
+// 32 entries' B columns are built in registers.  An output column (one
+// entry) lands in lanes j and j + 32, each with half of the rows; the rest
+// runs on the VALU in those two lanes, and the values a lane half lacks are
+// added with the partner lane (lane ^ 32).
+//
+// 4-way, rank 8: the core matricised as M[(j1 j2)][(j3 j4)] (64 x 64).  Two
+// products of depth 64 whose B columns are the Khatri-Rao products of the
+// entry's rows (Definition 1):
+//   S_e = M^T (u^(1) o u^(2))_e   (G x_1 u^(1) x_2 u^(2), over j3, j4)
+//   R_e = M   (u^(3) o u^(4))_e   (G x_3 u^(3) x_4 u^(4), over j1, j2)
+// and from them, with the division-free reuse of Algorithm 3,
+//   w_3 = S u^(4), w_4 = S^T u^(3), x~ = w_4 . u^(4),
+//   w_1 = R u^(2), w_2 = R^T u^(1).
+// Cost per entry: 2 J^N multiply-adds on the matrix cores, and on the VALU
+// the 2 J^2 Khatri-Rao products and 4 J^2 multiply-adds.
+//
+// 3-way, rank 16: the two mode products T1_e = G x_1 u^(1)_e and
+// TN_e = G x_3 u^(3)_e (tail 256, depth 16: eight 32-row tiles each); from
+// T1: x~, w_2 and w_3, from TN: w_1.  The tail order of each lane half is
+// chosen so that w_1 and w_2 are complete inside a lane.  Cost per entry:
+// 4 J^N multiply-adds on the matrix cores, about 3 J^(N-1) on the VALU.
 //
 // Operands: OP = kOpF32 uses v_mfma_f32_32x32x2f32 (FP32 inputs and sums);
 // OP = kOpBF16 uses v_mfma_f32_32x32x8bf16_1k (inputs rounded to BF16, round
 // to nearest even, FP32 sums).
-// Shapes: N = 4 with JP = 8 (tail 512, 16 tiles of 32 rows) and N = 3 with
-// JP = 16 (tail 256, 8 tiles).
 //
 // Lane layouts (checked on gfx950): 32x32x2f32: A[i][k] in lane i + 32 k,
 // B[k][j] in lane j + 32 k; 32x32x8bf16_1k: A[i][k] in lane i + 32 (k / 4),
@@ -44,19 +49,24 @@ typedef short s3_v4s __attribute__((ext_vector_type(4)));
 template <int N, int JP> constexpr bool mfma_shape() { return (N == 4 && JP == 8) || (N == 3 && JP == 16); }
 
 template <int N, int JP> struct MfmaDims {
-    static constexpr int TL = (N == 3) ? JP * JP : JP * JP * JP;  // tail of one product
-    static constexpr int NQ = TL / 32;                            // 32-row tiles
-    static constexpr int SLOT = N * JP + 4;                       // floats per entry slot in LDS
+    static constexpr int TL = JP * JP;                  // output rows of one product (64 or 256)
+    static constexpr int NQ = TL / 32;                  // 32-row tiles
+    static constexpr int KD = (N == 4) ? JP * JP : JP;  // depth of one product (64 or 16)
+    static constexpr int SLOT = N * JP + 4;             // floats per entry slot in LDS
 };
 
-template <int OP, int JP> struct MfmaOp {
-    static constexpr int NC = (OP == kOpBF16) ? JP / 8 : JP / 2;  // instructions per tile (K chunks)
+template <int OP, int KD> struct MfmaOp {
+    static constexpr int NC = (OP == kOpBF16) ? KD / 8 : KD / 2;  // instructions per tile (K chunks)
     static constexpr int V = (OP == kOpBF16) ? 4 : 1;             // operand values per lane per chunk
 };
 
-// bytes of the staged core operands (both products)
+// values and bytes of the staged core operands (both products)
+template <int N, int JP, int OP> constexpr int mfma_core_count() {
+    using O = MfmaOp<OP, MfmaDims<N, JP>::KD>;
+    return 2 * MfmaDims<N, JP>::NQ * kWave * O::NC * O::V;
+}
 template <int N, int JP, int OP> constexpr int mfma_core_bytes() {
-    return 2 * MfmaDims<N, JP>::NQ * kWave * MfmaOp<OP, JP>::NC * MfmaOp<OP, JP>::V * (OP == kOpBF16 ? 2 : 4);
+    return mfma_core_count<N, JP, OP>() * (OP == kOpBF16 ? 2 : 4);
 }
 
 // Two FP32 values to a BF16 pair (round to nearest even; one
@@ -71,29 +81,24 @@ S3_DEV s3_v4s bf16x4(float a, float b, float c, float d) {
     return s3_v4s{(short)(lo & 0xffffu), (short)(lo >> 16), (short)(hi & 0xffffu), (short)(hi >> 16)};
 }
 
-// Tail position held by output register r of tile q in lane half h.  With
-// (x, y, z) the tail's mode indices (modes 2..N for T1, 1..N-1 for TN):
-//   N = 4: pair pi = 2 q + r / 8, x = 4 h + pi / 8, y = pi % 8, z = r % 8, so
-//          half h owns x in [4h, 4h + 4) with every y and z;
-//   N = 3: x = 8 h + q, y = r, so half h owns x in [8h, 8h + 8).
-template <int N, int JP> S3_DEV int mfma_tail(int q, int h, int r) {
-    if constexpr (N == 4) {
-        const int pi = 2 * q + (r >> 3);
-        return ((4 * h + (pi >> 3)) * 8 + (pi & 7)) * 8 + (r & 7);
-    } else {
-        return (8 * h + q) * 16 + r;
-    }
-}
+// 3-way: tail position held by output register r of tile q in lane half h,
+// with (x, y) the tail's mode indices (modes 2, 3 for T1, 1, 2 for TN):
+// x = 8 h + q, y = r, so half h owns x in [8h, 8h + 8).
+S3_DEV int mfma_tail3(int q, int h, int r) { return (8 * h + q) * 16 + r; }
 
 // Stage the core operands of both products (all threads of the grid; Gp is
-// the zero-padded JP^N core, row-major).  Layout: product,
-// tile, lane, then the lane's chunks and values, so that a lane reads its
-// whole A operand of a tile with one or two wide loads.
+// the zero-padded JP^N core, row-major).  Layout: product, tile, lane, then
+// the lane's chunks and values, so that a lane reads its whole A operand of a
+// tile with wide loads.  Output row i of tile q is row 32 q + i of the
+// product; depth index k.
+//   4-way: product 0 is M^T (row (j3 j4), depth (j1 j2)), product 1 is M;
+//   3-way: product 0 is T1 (row = tail (j2 j3), depth j1), product 1 is TN
+//          (row = tail (j1 j2), depth j3).
 template <int N, int JP, int OP>
 S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *__restrict__ s_g) {
     using D = MfmaDims<N, JP>;
-    using O = MfmaOp<OP, JP>;
-    constexpr int total = 2 * D::NQ * kWave * O::NC * O::V;
+    using O = MfmaOp<OP, D::KD>;
+    constexpr int total = mfma_core_count<N, JP, OP>();
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
         const int v = x % O::V;
         int t = x / O::V;
@@ -104,9 +109,15 @@ S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *__restrict__ s_g
         const int q = t % D::NQ, prod = t / D::NQ;
         const int i = lane & 31, kh = lane >> 5;
         const int k = (OP == kOpBF16) ? 8 * c + 4 * kh + v : 2 * c + kh;
-        const int h = (i >> 2) & 1, r = 4 * (i >> 3) + (i & 3);
-        const int tail = mfma_tail<N, JP>(q, h, r);
-        const float g = (prod == 0) ? Gp[k * D::TL + tail] : Gp[tail * JP + k];
+        float g;
+        if constexpr (N == 4) {
+            const int row = 32 * q + i;
+            g = (prod == 0) ? Gp[k * 64 + row] : Gp[row * 64 + k];
+        } else {
+            const int h = (i >> 2) & 1, r = 4 * (i >> 3) + (i & 3);
+            const int tail = mfma_tail3(q, h, r);
+            g = (prod == 0) ? Gp[k * D::TL + tail] : Gp[tail * JP + k];
+        }
         if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[x] = (unsigned short)(bf16x2(g, 0.f) & 0xffffu);
         else ((float *)s_g)[x] = g;
     }
@@ -131,11 +142,12 @@ template <int N, int JP, int OP> S3_DEV void mfma_load_core(const void *__restri
     }
 }
 
-// B operand chunks of one entry row (the lane half kh takes its K values)
-template <int OP, int JP> struct MfmaB {
-    typename std::conditional<OP == kOpBF16, s3_v4s, float>::type c[MfmaOp<OP, JP>::NC];
+// B operand chunks of one entry column (the lane half kh takes its K values)
+template <int OP, int KD> struct MfmaB {
+    typename std::conditional<OP == kOpBF16, s3_v4s, float>::type c[MfmaOp<OP, KD>::NC];
 };
 
+// 3-way: the column is one of the entry's rows
 template <int OP, int JP> S3_DEV MfmaB<OP, JP> mfma_b_of(const float *row, int kh) {
     MfmaB<OP, JP> b;
 #pragma unroll
@@ -150,11 +162,31 @@ template <int OP, int JP> S3_DEV MfmaB<OP, JP> mfma_b_of(const float *row, int k
     return b;
 }
 
+// 4-way: the column is the Khatri-Rao product (a o b)[8 x + y] = a[x] b[y] of
+// two rows of 8, formed in FP32 (then rounded once for BF16 operands)
+template <int OP> S3_DEV MfmaB<OP, 64> mfma_b_kr(const float (&a)[8], const float (&b)[8], int kh) {
+    MfmaB<OP, 64> o;
+    if constexpr (OP == kOpBF16) {
+        float bh[4];  // depth 8 c + 4 kh + v: x = c, y = 4 kh + v
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bh[v] = kh ? b[4 + v] : b[v];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) o.c[c] = bf16x4(a[c] * bh[0], a[c] * bh[1], a[c] * bh[2], a[c] * bh[3]);
+    } else {
+        float bh[4];  // depth 2 c + kh: x = c / 4, y = 2 (c % 4) + kh
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bh[r] = kh ? b[2 * r + 1] : b[2 * r];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) o.c[c] = a[c >> 2] * bh[c & 3];
+    }
+    return o;
+}
+
 // One 32 x 32 output tile: product prod, tile q
 template <int N, int JP, int OP>
-S3_DEV s3_v16f mfma_tile(const void *s_g, int prod, int q, int lane, const MfmaB<OP, JP> &b) {
+S3_DEV s3_v16f mfma_tile(const void *s_g, int prod, int q, int lane, const MfmaB<OP, MfmaDims<N, JP>::KD> &b) {
     using D = MfmaDims<N, JP>;
-    using O = MfmaOp<OP, JP>;
+    using O = MfmaOp<OP, D::KD>;
     s3_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int base = ((prod * D::NQ + q) * kWave + lane) * O::NC * O::V;
     if constexpr (OP == kOpBF16) {
@@ -190,80 +222,75 @@ S3_DEV void mfma_contract_wave(float *slots, const void *s_g) {
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
         float *slot = slots + (32 * pass + j) * D::SLOT;
-        const MfmaB<OP, JP> bfirst = mfma_b_of<OP, JP>(slot, h);
-        const MfmaB<OP, JP> blast = mfma_b_of<OP, JP>(slot + (N - 1) * JP, h);
         if constexpr (N == 4) {
-            float b[8], c[8], d[8];
+            float a1[8], a2[8], a3[8], a4[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                b[k] = slot[8 + k];
-                c[k] = slot[16 + k];
-                d[k] = slot[24 + k];
-            }
-            float bh[4];  // u^(2) at this half's mode-2 indices 4h .. 4h + 3
+            for (int k = 0; k < 8; k += 4) {
+                const s3_v4f_m x1 = *(const s3_v4f_m *)(slot + k), x2 = *(const s3_v4f_m *)(slot + 8 + k);
+                const s3_v4f_m x3 = *(const s3_v4f_m *)(slot + 16 + k), x4 = *(const s3_v4f_m *)(slot + 24 + k);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) bh[k] = h ? b[4 + k] : b[k];
-            float R[4] = {0.f, 0.f, 0.f, 0.f}, w1l[4] = {0.f, 0.f, 0.f, 0.f};
-            float w3p[8], w4p[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) { w3p[k] = 0.f; w4p[k] = 0.f; }
-            // tiles q + 1 go to the matrix cores before tile q's results are used
-            s3_v16f t1 = mfma_tile<N, JP, OP>(s_g, 0, 0, lane, bfirst);
-            s3_v16f tn = mfma_tile<N, JP, OP>(s_g, 1, 0, lane, blast);
-#pragma unroll
-            for (int q = 0; q < D::NQ; ++q) {
-                s3_v16f t1n = t1, tnn = tn;
-                if (q + 1 < D::NQ) {
-                    t1n = mfma_tile<N, JP, OP>(s_g, 0, q + 1, lane, bfirst);
-                    tnn = mfma_tile<N, JP, OP>(s_g, 1, q + 1, lane, blast);
+                for (int v = 0; v < 4; ++v) {
+                    a1[k + v] = x1[v];
+                    a2[k + v] = x2[v];
+                    a3[k + v] = x3[v];
+                    a4[k + v] = x4[v];
                 }
-                // T1 tile: (j2, j3, j4) = (4h + pi / 8, pi % 8, r % 8), pi = 2q + r / 8
+            }
+            const MfmaB<OP, 64> b12 = mfma_b_kr<OP>(a1, a2, h);
+            const MfmaB<OP, 64> b34 = mfma_b_kr<OP>(a3, a4, h);
+            // S rows (j3 j4) = 32 t + 8 g + 4 h + v: j3 = 4 t + g, j4 = 4 h + v; R rows
+            // (j1 j2) likewise: j1 = 4 t + g, j2 = 4 h + v (register 4 g + v of tile t)
+            const s3_v16f S0 = mfma_tile<N, JP, OP>(s_g, 0, 0, lane, b12);
+            const s3_v16f S1 = mfma_tile<N, JP, OP>(s_g, 0, 1, lane, b12);
+            const s3_v16f R0 = mfma_tile<N, JP, OP>(s_g, 1, 0, lane, b34);
+            const s3_v16f R1 = mfma_tile<N, JP, OP>(s_g, 1, 1, lane, b34);
+            float a2h[4], a4h[4];  // u^(2), u^(4) at this half's indices 4h .. 4h + 3
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const int pi = 2 * q + s, jl = pi >> 3, j3 = pi & 7;
-                    const float bc = bh[jl] * c[j3];
-                    float S = 0.f;
+            for (int v = 0; v < 4; ++v) {
+                a2h[v] = h ? a2[4 + v] : a2[v];
+                a4h[v] = h ? a4[4 + v] : a4[v];
+            }
+            float w4h[4] = {0.f, 0.f, 0.f, 0.f}, w2h[4] = {0.f, 0.f, 0.f, 0.f};
+            float w3p[8], w1p[8];
 #pragma unroll
-                    for (int z = 0; z < 8; ++z) {
-                        S = fmaf(t1[8 * s + z], d[z], S);           // (T1 x_4 u4)[j2][j3]
-                        w4p[z] = fmaf(t1[8 * s + z], bc, w4p[z]);   // (T1 x_2 u2 x_3 u3)[j4]
+            for (int k = 0; k < 8; ++k) { w3p[k] = 0.f; w1p[k] = 0.f; }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int x = 4 * t + g;
+                        const float sv = t ? S1[4 * g + v] : S0[4 * g + v];
+                        const float rv = t ? R1[4 * g + v] : R0[4 * g + v];
+                        w4h[v] = fmaf(sv, a3[x], w4h[v]);    // w_4[4h + v] = sum_j3 S u^(3)
+                        w3p[x] = fmaf(sv, a4h[v], w3p[x]);   // w_3[j3], this half's j4
+                        w2h[v] = fmaf(rv, a1[x], w2h[v]);    // w_2[4h + v] = sum_j1 R u^(1)
+                        w1p[x] = fmaf(rv, a2h[v], w1p[x]);   // w_1[j1], this half's j2
                     }
-                    R[jl] = fmaf(S, c[j3], R[jl]);                   // w_2[j2]
-                    w3p[j3] = fmaf(S, bh[jl], w3p[j3]);              // w_3[j3] (this half's j2)
-                }
-                // TN tile: (j1, j2, j3) = (4h + pi / 8, pi % 8, r % 8)
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const int pi = 2 * q + s, jl = pi >> 3, j2 = pi & 7;
-                    float P = 0.f;
-#pragma unroll
-                    for (int z = 0; z < 8; ++z) P = fmaf(tn[8 * s + z], c[z], P);
-                    w1l[jl] = fmaf(P, b[j2], w1l[jl]);               // w_1[j1]
-                }
-                t1 = t1n;
-                tn = tnn;
-            }
             float xp = 0.f;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) xp = fmaf(R[k], bh[k], xp);
-            const float x = xp + __shfl_xor(xp, 32, kWave);
-            // this lane keeps indices 4h .. 4h + 3 of w_3 and w_4; the partner
+            for (int v = 0; v < 4; ++v) xp = fmaf(w4h[v], a4h[v], xp);
+            const float xt = xp + __shfl_xor(xp, 32, kWave);
+            // this lane keeps indices 4h .. 4h + 3 of w_1 and w_3; the partner
             // sends its partial sums at those indices
-            float w3o[4], w4o[4];
+            float w1o[4], w3o[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float s3 = h ? w3p[k] : w3p[4 + k], s4 = h ? w4p[k] : w4p[4 + k];
-                const float m3 = h ? w3p[4 + k] : w3p[k], m4 = h ? w4p[4 + k] : w4p[k];
+                const float s1 = h ? w1p[k] : w1p[4 + k], s3 = h ? w3p[k] : w3p[4 + k];
+                const float m1 = h ? w1p[4 + k] : w1p[k], m3 = h ? w3p[4 + k] : w3p[k];
+                w1o[k] = m1 + __shfl_xor(s1, 32, kWave);
                 w3o[k] = m3 + __shfl_xor(s3, 32, kWave);
-                w4o[k] = m4 + __shfl_xor(s4, 32, kWave);
             }
             // results in place (the pair's rows are no longer read)
-            *(s3_v4f_m *)(slot + 4 * h) = s3_v4f_m{w1l[0], w1l[1], w1l[2], w1l[3]};
-            *(s3_v4f_m *)(slot + 8 + 4 * h) = s3_v4f_m{R[0], R[1], R[2], R[3]};
+            *(s3_v4f_m *)(slot + 4 * h) = s3_v4f_m{w1o[0], w1o[1], w1o[2], w1o[3]};
+            *(s3_v4f_m *)(slot + 8 + 4 * h) = s3_v4f_m{w2h[0], w2h[1], w2h[2], w2h[3]};
             *(s3_v4f_m *)(slot + 16 + 4 * h) = s3_v4f_m{w3o[0], w3o[1], w3o[2], w3o[3]};
-            *(s3_v4f_m *)(slot + 24 + 4 * h) = s3_v4f_m{w4o[0], w4o[1], w4o[2], w4o[3]};
-            if (h == 0) slot[32] = x;
+            *(s3_v4f_m *)(slot + 24 + 4 * h) = s3_v4f_m{w4h[0], w4h[1], w4h[2], w4h[3]};
+            if (h == 0) slot[32] = xt;
         } else {
+            const MfmaB<OP, JP> bfirst = mfma_b_of<OP, JP>(slot, h);
+            const MfmaB<OP, JP> blast = mfma_b_of<OP, JP>(slot + (N - 1) * JP, h);
             float b[16], c[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {

@@ -204,7 +204,7 @@ template <int N, int JP, typename T, int CT = kReuse> struct Impl {
     static void mx_format(s3_plan *p, hipStream_t st) {
         if constexpr (is_mx(CT) && mfma_shape<N, JP>() && std::is_same<T, float>::value) {
             constexpr int OP = (CT == kMfma16) ? kOpBF16 : kOpF32;
-            constexpr int n = 2 * MfmaDims<N, JP>::NQ * kWave * MfmaOp<OP, JP>::NC * MfmaOp<OP, JP>::V;
+            constexpr int n = mfma_core_count<N, JP, OP>();
             hipLaunchKernelGGL((k_mx_format<N, JP, OP>), dim3((n + 255) / 256), dim3(256), 0, st, (const float *)p->Gp,
                                p->mx_g);
         }
