@@ -107,6 +107,11 @@ template <> S3_DEV uint32_t lf_cold<uint32_t>() { return 0xffffffffu; }
 // s_tab [G][H][JP + 1] (zeroed); between two barriers
 // ACC: the table already holds earlier tiles' sums (a workgroup that runs
 // several tiles), so a whole run is added to it rather than stored.
+// A thread takes work items tid, tid + kTile, ...; their chunk descriptors
+// are loaded kChunkBatch at a time before any is used, so the global loads
+// overlap instead of each waiting for the one before.
+constexpr int kChunkBatch = 8;
+
 template <int JP, int G, typename T, bool ACC = false>
 S3_DEV void lf_chunk_pass(const T *s_stage, T *s_tab, const uint32_t *chunks, const int32_t *nchunks, int H) {
     constexpr int W = JP + 1;
@@ -114,24 +119,40 @@ S3_DEV void lf_chunk_pass(const T *s_stage, T *s_tab, const uint32_t *chunks, co
     base[0] = 0;
 #pragma unroll
     for (int g = 0; g < G; ++g) base[g + 1] = base[g] + nchunks[g] * W;
-    for (int item = threadIdx.x; item < base[G]; item += kTile) {
-        int g = 0;
+    for (int i0 = threadIdx.x; i0 < base[G]; i0 += kChunkBatch * kTile) {
+        uint32_t d[kChunkBatch];
+        int gk[kChunkBatch];  // group * W + element
 #pragma unroll
-        for (int h = 1; h < G; ++h) g += item >= base[h];
-        const int c = (item - base[g]) / W, k = (item - base[g]) - c * W;
-        const uint32_t d = chunks[(size_t)g * kTile + c];
-        const int slot = d & 0xff, start = (d >> 8) & 0xff, len = ((d >> 16) & 0xf) + 1;
-        const T *src = s_stage + ((size_t)g * W + k) * kTile + start;
-        T sum = T(0);
+        for (int b = 0; b < kChunkBatch; ++b) {
+            const int item = i0 + b * kTile;
+            d[b] = 0;
+            gk[b] = 0;
+            if (item < base[G]) {
+                int g = 0;
 #pragma unroll
-        for (int j = 0; j < kRun; ++j)
-            if (j < len) sum += src[j];
-        T *dst = s_tab + ((size_t)g * H + slot) * W + k;
-        if ((d >> 20) & 1) {
-            if constexpr (ACC) *dst += sum;
-            else *dst = sum;
-        } else {
-            atomicAdd(dst, sum);
+                for (int h = 1; h < G; ++h) g += item >= base[h];
+                const int c = (item - base[g]) / W, k = (item - base[g]) - c * W;
+                d[b] = chunks[(size_t)g * kTile + c];
+                gk[b] = g * W + k;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kChunkBatch; ++b) {
+            if (i0 + b * kTile >= base[G]) break;
+            const int g = gk[b] / W, k = gk[b] - g * W;
+            const int slot = d[b] & 0xff, start = (d[b] >> 8) & 0xff, len = ((d[b] >> 16) & 0xf) + 1;
+            const T *src = s_stage + (size_t)gk[b] * kTile + start;
+            T sum = T(0);
+#pragma unroll
+            for (int j = 0; j < kRun; ++j)
+                if (j < len) sum += src[j];
+            T *dst = s_tab + ((size_t)g * H + slot) * W + k;
+            if ((d[b] >> 20) & 1) {
+                if constexpr (ACC) *dst += sum;
+                else *dst = sum;
+            } else {
+                atomicAdd(dst, sum);
+            }
         }
     }
 }
