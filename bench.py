@@ -35,6 +35,13 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 E_STAR = {"cfg2": 3, "cfg5": 3}
+# lock-free round size per workload (items per round): the 10M-entry
+# workload's held-out RMSE after 3 epochs worsens with larger rounds (1 %
+# margin left at 1,048,576), the 4-way workload's does not (1.3261-1.3311 over
+# 393,216-1,048,576), where 786,432 items (2,403 tensor tiles, 5 per
+# persistent workgroup) gave the shortest epoch
+ROUND_ITEMS = {"cfg5": 786432}
+DEFAULT_ROUND = 524288
 
 
 def log(msg):
@@ -168,7 +175,7 @@ def scaling_sweep(args):
         log(f"scaling point I={I:,} nnz={nnz:,}: generating")
         p = make_problem(cfg)
         U, G, V = init_params(cfg)
-        plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", damping=True, round_items=args.round_items,
+        plan = S3Plan.from_problem(p, (U, G, V), dtype="f32", damping=True, round_items=args.round_items or DEFAULT_ROUND,
                                    seed=args.seed, hot_rows=args.hot_rows)
         for e in range(args.warmup):
             plan.epoch(e, "lockfree")
@@ -224,6 +231,10 @@ def generate(args, config):
     return cfg, p, U, G, V
 
 
+def round_items(args, config):
+    return args.round_items or ROUND_ITEMS.get(config, DEFAULT_ROUND)
+
+
 def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     import torch
     from paper_1708_08640_amd import S3Plan
@@ -232,7 +243,7 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     n_updates = p.n_items
     order = item_order(p.n_items, args.seed, 0) if mode == "det" else None
     plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=args.batch, order=order, damping=True,
-                               round_items=args.round_items, seed=args.seed, hot_rows=args.hot_rows,
+                               round_items=round_items(args, config), seed=args.seed, hot_rows=args.hot_rows,
                                contraction=contraction, core=args.core)
     torch.cuda.synchronize()
     rmse0 = plan.rmse()
@@ -278,7 +289,7 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     mat_flops = sum(matrix_entry_flops(cfg.ranks[s.mode]) * len(p.mat_val[m]) for m, s in enumerate(cfg.matrices))
     secs = kernel_ms / 1e3
     kname = ("k_lf_tensor_mx" if contraction == "matrix" else "k_lf_tensor") if mode == "lockfree" else "k_det_entries"
-    default_shape = (args.scale == 1.0 and args.core == "tucker" and args.round_items == 524288
+    default_shape = (args.scale == 1.0 and args.core == "tucker" and args.round_items is None
                      and args.hot_rows == 64 and mode == "lockfree")
     traffic = profiled_traffic(kname, f"{config}_{dtype}") if default_shape else None
     if contraction == "matrix":
@@ -347,7 +358,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed epochs before the timed ones")
     ap.add_argument("--config", default="cfg5")
     ap.add_argument("--mode", default="lockfree", choices=["lockfree", "det"])
-    ap.add_argument("--round-items", type=int, default=524288)
+    ap.add_argument("--round-items", type=int, default=None,
+                    help="lock-free items per round (default: 786,432 for cfg5, 524,288 otherwise)")
     ap.add_argument("--hot-rows", type=int, default=64)
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--core", default="tucker", choices=["tucker", "cp"],
@@ -452,7 +464,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.description}", "mode": args.mode,
-                   "round_items": args.round_items if args.mode == "lockfree" else None,
+                   "round_items": round_items(args, args.config) if args.mode == "lockfree" else None,
                    "hot_rows": args.hot_rows if args.mode == "lockfree" else None,
                    "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
                    "contraction": ct, "core": args.core, "master_dtype": "f32",

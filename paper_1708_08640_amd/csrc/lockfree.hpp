@@ -704,6 +704,8 @@ struct LFApplyArgs {
     const void *core_t;                     // tensor core partials [nwg_t][KP+2]
     int64_t KP;                             // padded core size JP^N (JP: hyper-diagonal)
     int cp;                                 // hyper-diagonal core
+    void *mx_img;                           // matrix-core operand image of the core, kept current
+    int mx_kind;                            // 0: none; 1/2: 4-way BF16/FP32; 3/4: 3-way BF16/FP32
 };
 
 constexpr int kApplyThreads = 256;
@@ -837,6 +839,15 @@ __global__ __launch_bounds__(kApplyThreads) void k_lf_apply(LFApplyArgs a, int H
     const T gnew = G[j] - step * (gsum + cnt * reg_core * G[j]);
     G[j] = gnew;
     Gp[jp] = gnew;
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (N == 4) {
+            if (a.mx_kind == 1) mfma_image_write<4, 8, kOpBF16>(a.mx_img, (int)jp, gnew);
+            else if (a.mx_kind == 2) mfma_image_write<4, 8, kOpF32>(a.mx_img, (int)jp, gnew);
+        } else {
+            if (a.mx_kind == 3) mfma_image_write<3, 16, kOpBF16>(a.mx_img, (int)jp, gnew);
+            else if (a.mx_kind == 4) mfma_image_write<3, 16, kOpF32>(a.mx_img, (int)jp, gnew);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- metadata

@@ -130,6 +130,40 @@ __global__ __launch_bounds__(256) void k_mx_format(const float *__restrict__ Gp,
     mfma_stage_core<N, JP, OP>(Gp, out);
 }
 
+// One core value written into the operand image, at both of its places:
+// the inverse of mfma_stage_core's mapping, for a kernel that updates the
+// core element by element (jp: index in the zero-padded JP^N core).
+template <int N, int JP, int OP> S3_DEV void mfma_image_write(void *img, int jp, float g) {
+    using D = MfmaDims<N, JP>;
+    using O = MfmaOp<OP, D::KD>;
+#pragma unroll
+    for (int prod = 0; prod < 2; ++prod) {
+        int row, k;
+        if constexpr (N == 4) {
+            row = prod == 0 ? (jp & 63) : (jp >> 6);
+            k = prod == 0 ? (jp >> 6) : (jp & 63);
+        } else {
+            row = prod == 0 ? jp % D::TL : jp / JP;  // the tail
+            k = prod == 0 ? jp / D::TL : jp % JP;
+        }
+        int q, i;
+        if constexpr (N == 4) {
+            q = row >> 5;
+            i = row & 31;
+        } else {
+            const int x = row >> 4, r = row & 15, h = x >> 3;
+            q = x & 7;
+            i = 8 * (r >> 2) + 4 * h + (r & 3);
+        }
+        const int c = (OP == kOpBF16) ? k >> 3 : k >> 1;
+        const int kh = (OP == kOpBF16) ? (k >> 2) & 1 : k & 1;
+        const int v = (OP == kOpBF16) ? k & 3 : 0;
+        const int x = (((prod * D::NQ + q) * kWave + i + 32 * kh) * O::NC + c) * O::V + v;
+        if constexpr (OP == kOpBF16) ((unsigned short *)img)[x] = (unsigned short)(bf16x2(g, 0.f) & 0xffffu);
+        else ((float *)img)[x] = g;
+    }
+}
+
 // Copy the formatted operands into LDS (all threads of the block)
 template <int N, int JP, int OP> S3_DEV void mfma_load_core(const void *__restrict__ g, void *__restrict__ s_g) {
     constexpr int n16 = mfma_core_bytes<N, JP, OP>() / 16;

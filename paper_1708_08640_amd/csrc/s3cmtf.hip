@@ -904,7 +904,6 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
                 if (e0 && e1) p->pev_used += 2;
                 else e0 = e1 = nullptr;
             }
-            p->ks.mx_format(p, s_);  // the core as the last round left it
             return p->ks.lf_tensor(p, f, c, e, s_, e0, e1);
         };
         if (p->tsize == 8) {
@@ -912,6 +911,12 @@ s3_status s3_epoch(s3_plan *p, int32_t epoch, int32_t mode, void *stream) {
             s = lockfree_epoch<double>(p->lf, p->d, epoch, eta, (double *)p->Gp, st, p->err, round);
         } else {
             pad_core<float>(p, st);
+            // matrix-core plans: the core's operand image is formatted once
+            // here; each round's apply then rewrites the values it changes
+            const bool mx = p->d.contraction == S3_CONTRACT_MATRIX;
+            p->lf.apply.mx_img = mx ? p->mx_g : nullptr;
+            p->lf.apply.mx_kind = mx ? 1 + (p->N == 4 ? 0 : 2) + (p->d.dtype == S3_BF16 ? 0 : 1) : 0;
+            p->ks.mx_format(p, st);
             s = lockfree_epoch<float>(p->lf, p->d, epoch, eta, (float *)p->Gp, st, p->err, round);
         }
         HIPCHK(p, hipEventRecord(p->ev1, st));
