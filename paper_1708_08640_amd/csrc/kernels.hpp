@@ -672,9 +672,20 @@ S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict_
 #pragma unroll
         for (int k = 0; k < JP; k += 4)
             *(s3_v4f_m *)(mine + n * JP + k) = s3_v4f_m{u[n][k], u[n][k + 1], u[n][k + 2], u[n][k + 3]};
+    // the value (or upstream gradient) and the regularisers load during the
+    // contraction
+    constexpr bool train = !ADJ;
+    T xv = T(0), regs[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) regs[n] = T(0);
+    if (live) {
+        xv = ADJ ? gx[e] : A.val[e];
+#pragma unroll
+        for (int n = 0; n < N; ++n) regs[n] = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
+    }
     __syncthreads();  // slots and the staged core
     mfma_contract_wave<N, JP, OP>(slots, s_g);
-    __syncthreads();
+    wave_lds_sync();  // a wavefront reads back only its own slots
     T w[N][JP];
 #pragma unroll
     for (int n = 0; n < N; ++n)
@@ -690,13 +701,11 @@ S3_DEV void det_tensor_mx(const TensorArgs<float> &A, const int32_t *__restrict_
     __syncthreads();  // s_buf is reused for the core-gradient operands
     T q = T(0), curv = T(0);
     if (live) {
-        const T xv = ADJ ? gx[e] : A.val[e];
-        constexpr bool train = !ADJ;
         q = train ? -(xv - xhat) : xv;
         T *out = scr + s * stride;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            const T reg = train ? A.lambda_reg / (T)A.cnt[n][rows[n]] : T(0);
+            const T reg = regs[n];
             T ww = T(0);
 #pragma unroll
             for (int k = 0; k < JP; ++k) {

@@ -585,9 +585,12 @@ __global__ __launch_bounds__(kTile, 2) void k_lf_tensor_mx(TensorArgs<float> A, 
 #pragma unroll
             for (int k = 0; k < JP; k += 4)
                 *(s3_v4f_m *)(mine + n * JP + k) = s3_v4f_m{u[n][k], u[n][k + 1], u[n][k + 2], u[n][k + 3]};
-        __syncthreads();  // slots (and, first time, the staged core and zeroed tables)
+        // a wavefront contracts only its own slots, so it waits only for
+        // itself, except before the first tile (staged core, zeroed tables)
+        if (first) __syncthreads();
+        else wave_lds_sync();
         mfma_contract_wave<N, JP, OP>(slots, s_g);
-        __syncthreads();
+        wave_lds_sync();
         T w[N][JP];
 #pragma unroll
         for (int n = 0; n < N; ++n)

@@ -244,6 +244,15 @@ S3_DEV s3_v16f mfma_tile(const void *s_g, int prod, int q, int lane, const MfmaB
     return acc;
 }
 
+// Order this wavefront's LDS writes before its later LDS reads (by any of its
+// lanes): the wavefront's LDS instructions complete in issue order, so only
+// the compiler has to be kept from moving them.
+S3_DEV void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The wavefront's 64 entries: slot s (s = 0..63) of `slots` holds entry s's
 // rows u^(1) | ... | u^(N) (JP each, zero padded) and receives, in place,
 // w_1 | ... | w_N | x~.  Every lane of the wavefront must call it.
