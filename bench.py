@@ -42,6 +42,11 @@ E_STAR = {"cfg2": 3, "cfg5": 3}
 # persistent workgroup) gave the shortest epoch
 ROUND_ITEMS = {"cfg5": 786432}
 DEFAULT_ROUND = 524288
+# det-mode batch per workload: on the 4-way workload the batch of the stored
+# det oracle trajectory (larger batches: fewer launches and a lower RMSE per
+# epoch there), 65,536 otherwise
+DET_BATCH = {"cfg5": 524288}
+DEFAULT_BATCH = 65536
 
 
 def log(msg):
@@ -235,6 +240,22 @@ def round_items(args, config):
     return args.round_items or ROUND_ITEMS.get(config, DEFAULT_ROUND)
 
 
+def det_batch(args, config):
+    return args.batch or DET_BATCH.get(config, DEFAULT_BATCH)
+
+
+def oracle_det_trajectory(config, batch, epochs):
+    """Mean over item orders of the stored det oracle RMSE after epochs
+    1..epochs at this batch size (None where not stored)."""
+    import glob
+    runs = []
+    for f in glob.glob(os.path.join(ROOT, "tests", "golden", f"{config}_det{batch}_s*.json")):
+        with open(f) as fh:
+            runs.append(json.load(fh)["rmse"])
+    return [float(np.mean([r[e] for r in runs if len(r) > e])) if any(len(r) > e for r in runs) else None
+            for e in range(epochs)]
+
+
 def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     import torch
     from paper_1708_08640_amd import S3Plan
@@ -242,7 +263,7 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     cfg, p, U, G, V = data
     n_updates = p.n_items
     order = item_order(p.n_items, args.seed, 0) if mode == "det" else None
-    plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=args.batch, order=order, damping=True,
+    plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=det_batch(args, config), order=order, damping=True,
                                round_items=round_items(args, config), seed=args.seed, hot_rows=args.hot_rows,
                                contraction=contraction, core=args.core)
     torch.cuda.synchronize()
@@ -345,7 +366,7 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     torch.cuda.empty_cache()
     if cpu:
         log(f"timing the FP64 oracle on {args.cpu_sample:,} items (CPU baseline)")
-        out["cpu"] = cpu_baseline(cfg, p, U, G, V, args.cpu_sample, args.seed, args.batch)
+        out["cpu"] = cpu_baseline(cfg, p, U, G, V, args.cpu_sample, args.seed, DEFAULT_BATCH)
         log(f"oracle: {out['cpu']['value']:.0f} updates/s ({out['cpu']['cores']} threads), sequential "
             f"{out['cpu']['sequential_sgd_value']:.0f}")
     return out
@@ -361,7 +382,8 @@ def main():
     ap.add_argument("--round-items", type=int, default=None,
                     help="lock-free items per round (default: 786,432 for cfg5, 524,288 otherwise)")
     ap.add_argument("--hot-rows", type=int, default=64)
-    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--batch", type=int, default=None,
+                    help="det-mode items per batch (default: 524,288 for cfg5, 65,536 otherwise)")
     ap.add_argument("--core", default="tucker", choices=["tucker", "cp"],
                     help="cp: the hyper-diagonal core (the CP special case), measured against the HBM roof")
     ap.add_argument("--contraction", default=None, choices=["reuse", "naive", "matrix"],
@@ -442,7 +464,10 @@ def main():
         # the deterministic mini-batch mode on the same workload and operands
         d = run(args, data, args.config, ct, dt, "det", args.steps, args.warmup)
         extra["det_mode"] = {
-            "dtype": dt, "contraction": ct, "batch": args.batch, "damping": "curvature", "value": d["value"],
+            "dtype": dt, "contraction": ct, "batch": det_batch(args, args.config), "damping": "curvature",
+            "value": d["value"],
+            "oracle_det_rmse_trajectory": oracle_det_trajectory(args.config, det_batch(args, args.config),
+                                                                len(d["rmse_trajectory"])),
             "unit": "updates/s", "ms_per_step": d["ms_per_step"], "heldout_rmse": d["heldout_rmse"],
             "rmse_epochs": d["rmse_epochs"], "rmse_trajectory": d["rmse_trajectory"], "rmse_ok": d["rmse_ok"],
             "roofline": d["roofline"]}
@@ -466,7 +491,7 @@ def main():
         "config": {"workload": f"{cfg.name}: {cfg.description}", "mode": args.mode,
                    "round_items": round_items(args, args.config) if args.mode == "lockfree" else None,
                    "hot_rows": args.hot_rows if args.mode == "lockfree" else None,
-                   "batch": args.batch if args.mode == "det" else None, "damping": "curvature",
+                   "batch": det_batch(args, args.config) if args.mode == "det" else None, "damping": "curvature",
                    "contraction": ct, "core": args.core, "master_dtype": "f32",
                    "updates_per_epoch": head["updates_per_epoch"], "parallelism": "single GPU"},
         "heldout_rmse": head["heldout_rmse"], "heldout_rmse_init": head["heldout_rmse_init"],

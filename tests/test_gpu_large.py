@@ -6,7 +6,9 @@
 * the same shape with 100M entries and core 16^3: the matrix-core
   contraction, FP32 and BF16 operands;
 * 4-way 1M x 500K x 1000 x 24, 200M entries, core 8^4, three coupled
-  matrices (one of them dense): the matrix-core contraction, FP32 and BF16.
+  matrices (one of them dense): the matrix-core contraction, FP32 and BF16;
+  also two whole det epochs (batches of 524,288) against the stored FP64 det
+  oracle trajectory.
 
 Each is checked on outputs the oracle can compute at full size: the first
 det batch (65,536 items) as an update from the same start (the bounds of
@@ -172,3 +174,29 @@ def test_large_matrix_core(name):
     for dtype in ("f32", "bf16"):
         _det_first_batch(cfg, p, params, order, dtype, "matrix")
     _lockfree_epoch(cfg, p, params, "bf16", "matrix")
+    if name == "cfg5":
+        _det_epochs_against_stored_oracle(cfg, p, params, order)
+
+
+def _det_epochs_against_stored_oracle(cfg, p, params, order):
+    """Two whole det epochs (batches of 524,288, damped, BF16 operands) on all
+    230M items: the held-out RMSE after each against the stored FP64 det
+    oracle trajectory with the same item order and FP32-rounded inputs
+    (tests/golden/cfg5_det524288_s7.json), to 1e-4 relative."""
+    import json
+    from paper_1708_08640_amd import S3Plan
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg5_det524288_s7.json")) as f:
+        ref = json.load(f)["rmse"]
+    plan = S3Plan.from_problem(p, params, dtype="bf16", damping=True, seed=SEED, batch=524288, order=order,
+                               contraction="matrix")
+    got = []
+    for e in range(min(2, len(ref))):
+        plan.epoch(e, "det")
+        got.append(plan.rmse())
+    del plan
+    torch.cuda.empty_cache()
+    print(f"[large] cfg5 det epochs (BF16, batches of 524,288): RMSE {got} against the oracle's {ref[:len(got)]}",
+          flush=True)
+    assert got, "no stored det oracle epochs"
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= 1e-4 * r
