@@ -202,7 +202,7 @@ def _bucket_of(keys: np.ndarray, nbucket: int) -> np.ndarray:
 def _fresh_positions(keys: np.ndarray, runs: List[List[np.ndarray]]) -> np.ndarray:
     """Positions of the keys of one draw that occur there for the first time
     and are not in the kept set (runs: per hash bucket, 1 or 256 of them,
-    sorted runs of kept keys), which they join; increasing positions."""
+    sorted disjoint runs of kept keys), which they join; increasing positions."""
     nbucket = len(runs)
     b = _bucket_of(keys, nbucket)
     perm = np.argsort(b, kind="stable")  # draw order kept within a bucket
@@ -224,12 +224,20 @@ def _fresh_positions(keys: np.ndarray, runs: List[List[np.ndarray]]) -> np.ndarr
             seen |= r[at] == cand
         keep = ~seen
         if keep.any():
-            runs[j].append(cand[keep])
-            if len(runs[j]) > 8:  # fold the small runs into one
-                runs[j][:] = [runs[j][0], np.sort(np.concatenate(runs[j][1:]))]
+            rs = runs[j]
+            rs.append(cand[keep])
+            # merge runs of similar size (sizes at least halve from the
+            # first run on), so a bucket holds O(log n) runs
+            while len(rs) > 1 and 2 * rs[-1].size >= rs[-2].size:
+                top = rs.pop()
+                rs[-1] = np.sort(np.concatenate([rs[-1], top]))
         return pos[keep]
 
-    pos = np.concatenate(_map(work, range(nbucket)) if nbucket > 1 else [work(0)])
+    if nbucket > 1 and keys.size >= 65536:
+        parts = _map(work, range(nbucket))
+    else:  # small draws: the thread hand-offs would cost more than the work
+        parts = [work(j) for j in range(nbucket) if bounds[j + 1] > bounds[j]]
+    pos = np.concatenate(parts) if parts else np.empty(0, dtype=np.int64)
     pos.sort()
     return pos
 
