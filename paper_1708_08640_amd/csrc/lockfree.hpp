@@ -20,10 +20,17 @@
 //          whole hot-row
 //          table and core partial to its own slot of a partials buffer
 //          (plain coalesced stores: no global atomics).
+//   k_lf_tensor_mx  the same with the dense part of the contraction on the
+//          matrix cores (mfma.hpp): persistent workgroups, each running
+//          ceil(tiles / 512) of the round's tiles with the core's operand
+//          image staged once and its hot table and core partial carried
+//          from tile to tile; each tile's entry streams are loaded while the
+//          tile before it runs.
 //   k_lf_apply  one workgroup per hot row and one per 16 core elements:
 //          sums the round's partials of every workgroup in a fixed order and
 //          moves the row / the core once by the damped step
-//          -eta sum g / max(1, k eta sum L).
+//          -eta sum g / max(1, k eta sum L); for matrix-core plans it also
+//          rewrites the core values it changes in the operand image.
 // "Hot" rows are the H most frequent rows of each mode and of each coupled
 // factor.  The paper lets one worker own the core, which every entry
 // touches; power-law data (a handful of rows in 10-30 % of all entries)
