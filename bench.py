@@ -71,11 +71,17 @@ def matrix_entry_flops(rank):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources' code (comments and blank space removed, so
+    that editing a comment does not orphan the committed counter summaries)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("common.hpp", "contract.hpp", "kernels.hpp", "lockfree.hpp", "mfma.hpp", "plan.hpp"):
-        with open(os.path.join(ROOT, "paper_1708_08640_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1708_08640_amd", "csrc", f)) as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
