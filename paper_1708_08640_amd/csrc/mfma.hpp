@@ -69,6 +69,19 @@ template <int N, int JP, int OP> constexpr int mfma_core_bytes() {
     return mfma_core_count<N, JP, OP>() * (OP == kOpBF16 ? 2 : 4);
 }
 
+// Place of operand element (lane, chunk c, value v) of tile q of product prod
+// in the staged image.  A lane's values come in 16-byte groups, and group g
+// of all 64 lanes is stored contiguously, so that a wavefront's wide LDS reads
+// of one group touch consecutive bank quads.
+template <int N, int JP, int OP> S3_DEV int mfma_img_index(int prod, int q, int lane, int c, int v) {
+    using D = MfmaDims<N, JP>;
+    using O = MfmaOp<OP, D::KD>;
+    constexpr int E = O::NC * O::V;              // values per lane
+    constexpr int GV = (OP == kOpBF16) ? 8 : 4;  // values per 16-byte group
+    const int e = c * O::V + v;
+    return (prod * D::NQ + q) * kWave * E + ((e / GV) * kWave + lane) * GV + e % GV;
+}
+
 // Two FP32 values to a BF16 pair (round to nearest even; one
 // v_cvt_pk_bf16_f32), low half first
 typedef __bf16 s3_bf2 __attribute__((ext_vector_type(2)));
@@ -87,10 +100,9 @@ S3_DEV s3_v4s bf16x4(float a, float b, float c, float d) {
 S3_DEV int mfma_tail3(int q, int h, int r) { return (8 * h + q) * 16 + r; }
 
 // Stage the core operands of both products (all threads of the grid; Gp is
-// the zero-padded JP^N core, row-major).  Layout: product, tile, lane, then
-// the lane's chunks and values, so that a lane reads its whole A operand of a
-// tile with wide loads.  Output row i of tile q is row 32 q + i of the
-// product; depth index k.
+// the zero-padded JP^N core, row-major), each value at mfma_img_index of its
+// (product, tile, lane, chunk, value).  Output row i of tile q is row 32 q + i
+// of the product; depth index k.
 //   4-way: product 0 is M^T (row (j3 j4), depth (j1 j2)), product 1 is M;
 //   3-way: product 0 is T1 (row = tail (j2 j3), depth j1), product 1 is TN
 //          (row = tail (j1 j2), depth j3).
@@ -118,8 +130,9 @@ S3_DEV void mfma_stage_core(const float *__restrict__ Gp, void *__restrict__ s_g
             const int tail = mfma_tail3(q, h, r);
             g = (prod == 0) ? Gp[k * D::TL + tail] : Gp[tail * JP + k];
         }
-        if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[x] = (unsigned short)(bf16x2(g, 0.f) & 0xffffu);
-        else ((float *)s_g)[x] = g;
+        const int y = mfma_img_index<N, JP, OP>(prod, q, lane, c, v);
+        if constexpr (OP == kOpBF16) ((unsigned short *)s_g)[y] = (unsigned short)(bf16x2(g, 0.f) & 0xffffu);
+        else ((float *)s_g)[y] = g;
     }
 }
 
@@ -158,7 +171,7 @@ template <int N, int JP, int OP> S3_DEV void mfma_image_write(void *img, int jp,
         const int c = (OP == kOpBF16) ? k >> 3 : k >> 1;
         const int kh = (OP == kOpBF16) ? (k >> 2) & 1 : k & 1;
         const int v = (OP == kOpBF16) ? k & 3 : 0;
-        const int x = (((prod * D::NQ + q) * kWave + i + 32 * kh) * O::NC + c) * O::V + v;
+        const int x = mfma_img_index<N, JP, OP>(prod, q, i + 32 * kh, c, v);
         if constexpr (OP == kOpBF16) ((unsigned short *)img)[x] = (unsigned short)(bf16x2(g, 0.f) & 0xffffu);
         else ((float *)img)[x] = g;
     }
@@ -222,17 +235,21 @@ S3_DEV s3_v16f mfma_tile(const void *s_g, int prod, int q, int lane, const MfmaB
     using D = MfmaDims<N, JP>;
     using O = MfmaOp<OP, D::KD>;
     s3_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int base = ((prod * D::NQ + q) * kWave + lane) * O::NC * O::V;
+    // the lane's 16-byte groups (mfma_img_index): two chunks each for BF16,
+    // four for FP32
     if constexpr (OP == kOpBF16) {
-        const s3_v4s *a = (const s3_v4s *)((const unsigned short *)s_g + base);
+        const unsigned short *a = (const unsigned short *)s_g + mfma_img_index<N, JP, OP>(prod, q, lane, 0, 0);
 #pragma unroll
-        for (int c = 0; c < O::NC; ++c) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[c], b.c[c], acc, 0, 0, 0);
+        for (int c = 0; c < O::NC; ++c) {
+            const s3_v4s av = *(const s3_v4s *)(a + (c >> 1) * kWave * 8 + (c & 1) * 4);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, b.c[c], acc, 0, 0, 0);
+        }
     } else {
-        const float *a = (const float *)s_g + base;
+        const float *a = (const float *)s_g + mfma_img_index<N, JP, OP>(prod, q, lane, 0, 0);
         float av[O::NC];
 #pragma unroll
         for (int c = 0; c < O::NC; c += 4) {
-            const s3_v4f_m t = *(const s3_v4f_m *)(a + c);  // 16-byte aligned: NC is a multiple of 4
+            const s3_v4f_m t = *(const s3_v4f_m *)(a + (c >> 2) * kWave * 4);  // 16-byte aligned group
             av[c] = t[0];
             av[c + 1] = t[1];
             av[c + 2] = t[2];
