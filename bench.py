@@ -406,7 +406,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0,
                     help="profiling runs only: entry counts of the tensor and of the sparse matrices times this "
                          "(same dimensions, ranks and rounds)")
-    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--scaling", choices=["dims", "nnz"], default=None,
