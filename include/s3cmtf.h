@@ -104,17 +104,22 @@ enum { S3_DAMP_NONE = 0, S3_DAMP_CURVATURE = 1 };       /* s3_desc.damping */
 /* Per-entry contraction (s3_desc.contraction). */
 #define S3_CONTRACT_REUSE 0
 #define S3_CONTRACT_NAIVE 1
-#define S3_CONTRACT_MATRIX 2  /* the dense part on the matrix cores: the mode
-                                 products G x_1 u^(1) and G x_N u^(N) of 32
-                                 entries at a time as (J^(N-1) x J) . (J x 32)
-                                 products, the rest of Eq (8)'s contractions
-                                 reusing them on the vector units (Algorithm 3's
-                                 reuse of partial products); the core gradient
-                                 of each 256-entry tile on the matrix cores too.
-                                 Operands FP32 (S3_F32) or BF16 (S3_BF16), sums
-                                 in FP32.  Built for 3-way tensors with padded
-                                 rank 16 (ranks 13..16) and 4-way tensors with
-                                 padded rank 8 (ranks 5..8)                   */
+#define S3_CONTRACT_MATRIX 2  /* the dense part on the matrix cores, 32
+                                 entries at a time: 3-way, the mode products
+                                 G x_1 u^(1) and G x_3 u^(3) as (J^2 x J) .
+                                 (J x 32) products; 4-way, G x_1 u^(1) x_2 u^(2)
+                                 and G x_3 u^(3) x_4 u^(4) as (J^2 x J^2) .
+                                 (J^2 x 32) products whose columns are the
+                                 entries' Khatri-Rao products (Definition 1).
+                                 The rest of Eq (8)'s contractions reuse them
+                                 on the vector units (Algorithm 3's reuse of
+                                 partial products, without its divisions); the
+                                 core gradient of each 256-entry tile runs on
+                                 the matrix cores too.  Operands FP32 (S3_F32)
+                                 or BF16 (S3_BF16), sums in FP32.  Built for
+                                 3-way tensors with padded rank 16 (ranks
+                                 13..16) and 4-way tensors with padded rank 8
+                                 (ranks 5..8)                                 */
 
 /* Core structure (s3_desc.core_kind). */
 #define S3_CORE_TUCKER 0   /* dense core J_1 x ... x J_N (Eq 4)             */
@@ -197,15 +202,21 @@ s3_status s3_plan_create(const s3_desc *desc, s3_plan **plan);
 s3_status s3_plan_destroy(s3_plan *plan);
 
 /* Bytes of device workspace s3_bind needs for these entry counts
- * (x_nnz, t_nnz, y_nnz[M]).  Host only.                                  */
+ * (x_nnz, t_nnz, y_nnz[M]), with the det-mode structures included.  Host
+ * only.  S3_ERR_UNSUPPORTED if the det-mode structures of these counts do
+ * not fit their 32-bit fields (a batch's scratch beyond 2^32 values, or
+ * batches x (M + 1) beyond 2^32).                                         */
 s3_status s3_workspace_size(const s3_plan *plan, int64_t x_nnz, int64_t t_nnz,
                             const int64_t *y_nnz, size_t *bytes);
 
 /* Bind buffers and a workspace of ws_bytes at d_ws (device).  On the device
  * it checks every index against its mode / matrix size (S3_ERR_INDEX_RANGE
  * and nothing bound if one is out of range), builds the counts
- * |Omega_X^{n,i}| and |Omega_Y^{2,k}| of Eq (7), and the fixed per-batch
- * reduction order of det mode.  Synchronises `stream`.                    */
+ * |Omega_X^{n,i}| and |Omega_Y^{2,k}| of Eq (7), and, when buf->order is
+ * given, the fixed per-batch reduction order of det mode (S3_ERR_UNSUPPORTED,
+ * before any device access, if it would overflow its 32-bit fields; see
+ * s3_workspace_size).  S3_ERR_WORKSPACE if ws_bytes is too small.
+ * Synchronises `stream`.                                                  */
 s3_status s3_bind(s3_plan *plan, const s3_buffers *buf, void *d_ws, size_t ws_bytes,
                   void *stream);
 
