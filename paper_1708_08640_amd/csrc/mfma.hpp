@@ -24,7 +24,7 @@
 // TN_e = G x_3 u^(3)_e (tail 256, depth 16: eight 32-row tiles each); from
 // T1: x~, w_2 and w_3, from TN: w_1.  The tail order of each lane half is
 // chosen so that w_1 and w_2 are complete inside a lane.  Cost per entry:
-// 4 J^N multiply-adds on the matrix cores, about 3 J^(N-1) on the VALU.
+// 2 J^N multiply-adds on the matrix cores, about 3 J^(N-1) on the VALU.
 //
 // Operands: OP = kOpF32 uses v_mfma_f32_32x32x2f32 (FP32 inputs and sums);
 // OP = kOpBF16 uses v_mfma_f32_32x32x8bf16_1k (inputs rounded to BF16, round
