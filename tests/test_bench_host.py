@@ -1,0 +1,57 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic work per entry behind
+the roofline, the fixed-RMSE target from the stored oracle trajectories, and
+the counter-summary lookup."""
+import json
+import os
+
+import numpy as np
+
+import bench
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_work_per_entry():
+    # VALU single pass: 4K contraction + 2K core gradient + 10 per row element
+    assert bench.tensor_entry_flops((10, 10, 10)) == 6 * 1000 + 10 * 30
+    # matrix cores: two dense products (2 J^N multiply-adds each, in flops)
+    # and the core gradient; VALU: Khatri-Rao columns, four contractions of
+    # J^2 values, x~, and the row updates
+    mx, valu = bench.mx_entry_work((8, 8, 8, 8))
+    assert mx == 6 * 8 ** 4
+    assert valu == (64 + 64) + 4 * (64 + 64) + 2 * 8 + 10 * 32
+    mx3, valu3 = bench.mx_entry_work((16, 16, 16))
+    assert mx3 == 6 * 16 ** 3 and valu3 == 6 * 256 + 10 * 48
+    assert bench.matrix_entry_flops(8) == 80
+
+
+def test_rmse_target_is_1_01_times_the_stored_sgd_mean():
+    def finite_at(name, epoch):
+        with open(os.path.join(HERE, "golden", name)) as f:
+            r = json.load(f)["rmse"]
+        return r[epoch - 1] if len(r) >= epoch and np.all(np.isfinite(r[:epoch])) else None
+
+    names = [n for n in os.listdir(os.path.join(HERE, "golden")) if n.startswith("cfg2_sgd_s")]
+    vals = [v for v in (finite_at(n, 3) for n in names) if v is not None]
+    target, sgd, det = bench.oracle_target("cfg2", 3)
+    assert vals and abs(sgd - np.mean(vals)) < 1e-12 and abs(target - 1.01 * sgd) < 1e-12
+    assert det is not None and det < sgd
+    traj = bench.oracle_det_trajectory("cfg5", 524288, 2)
+    assert all(t is not None for t in traj) and traj[1] < traj[0]
+    assert bench.oracle_target("no_such_workload", 3) == (None, None, None)
+
+
+def test_traffic_lookup_follows_the_kernel_code():
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    # a committed summary is used only while its hash matches the sources
+    for kernel, workload in (("k_lf_tensor_mx", "cfg5_bf16"), ("k_lf_tensor", "cfg2_f32")):
+        path = os.path.join(bench.ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
+        with open(path) as f:
+            text = f.read()
+        fields = dict(line.split(":", 1) for line in text.splitlines()
+                      if ":" in line and not line.startswith(("#", " ", "|")))
+        stored = fields["source_sha256_16"].strip()
+        expect = int(fields["traffic_bytes_per_launch"]) if stored == h else None
+        assert bench.profiled_traffic(kernel, workload) == expect
+    assert bench.profiled_traffic("k_lf_tensor_mx", "no_such_workload") is None
