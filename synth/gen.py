@@ -242,6 +242,22 @@ def _fresh_positions(keys: np.ndarray, runs: List[List[np.ndarray]]) -> np.ndarr
     return pos
 
 
+# coordinate spaces up to this size keep their set as a byte map (one byte
+# per possible coordinate) instead of sorted runs of keys
+_MAP_LIMIT = 1 << 29
+
+
+def _fresh_positions_map(keys: np.ndarray, seen: np.ndarray) -> np.ndarray:
+    """_fresh_positions for a byte map of the kept set (same result)."""
+    idx = np.flatnonzero(seen[keys] == 0)
+    if idx.size == 0:
+        return idx
+    _, first = np.unique(keys[idx], return_index=True)  # first occurrence in the draw
+    pos = np.sort(idx[first])
+    seen[keys[pos]] = 1
+    return pos
+
+
 def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) -> np.ndarray:
     """Draw n distinct coordinate tuples; draw(k) returns int64 [len(dims), k].
 
@@ -254,15 +270,20 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) 
     total = int(strides[0]) * int(dims[0])
     if n > total:
         raise ValueError(f"{n} distinct entries requested from a space of {total}")
-    # hash buckets (searched by the worker threads) for large sets
-    runs: List[List[np.ndarray]] = [[] for _ in range(256 if n >= (1 << 20) else 1)]
+    if total <= _MAP_LIMIT:
+        seen = np.zeros(total, dtype=np.uint8)
+        fresh = lambda keys: _fresh_positions_map(keys, seen)  # noqa: E731
+    else:
+        # hash buckets (searched by the worker threads) for large sets
+        runs: List[List[np.ndarray]] = [[] for _ in range(256 if n >= (1 << 20) else 1)]
+        fresh = lambda keys: _fresh_positions(keys, runs)  # noqa: E731
     n_kept = 0
     kept = []
     need = n
     for _ in range(max_rounds):
         c = draw(need)
         keys = (c * strides[:, None]).sum(axis=0)
-        pos = _fresh_positions(keys, runs)
+        pos = fresh(keys)
         kept.append(c[:, pos])
         n_kept += pos.size
         need = n - n_kept
