@@ -213,11 +213,12 @@ def _fresh_positions(keys: np.ndarray, runs: List[List[np.ndarray]]) -> np.ndarr
         if idx.size == 0:
             return idx
         sub = keys[idx]
-        o = np.argsort(sub, kind="stable")
+        o = np.argsort(sub)  # not stable: a run of equal keys takes its smallest position below
         srt = sub[o]
         first = np.ones(srt.size, dtype=bool)
         first[1:] = srt[1:] != srt[:-1]
-        cand, pos = srt[first], idx[o[first]]
+        starts = np.flatnonzero(first)
+        cand, pos = srt[starts], np.minimum.reduceat(idx[o], starts)  # idx increases: draw order
         seen = np.zeros(cand.size, dtype=bool)
         for r in runs[j]:
             at = np.minimum(np.searchsorted(r, cand), r.size - 1)
