@@ -181,7 +181,8 @@ typedef struct {
     void *G;
     void *V[S3_MAX_MATRICES];
     /* det mode: the item order, a permutation of 0..n_items-1 (n_items =
-     * x_nnz + sum y_nnz), int32.  May be null if det mode is never run.   */
+     * x_nnz + sum y_nnz), int32.  May be null if det mode is never run
+     * (s3_backward then sums in the storage order).                      */
     const int32_t *order;
 } s3_buffers;
 
@@ -277,8 +278,15 @@ s3_status s3_predict_matrix(s3_plan *plan, int32_t m, const int32_t *row, const 
  *   dG    = sum_e gx[e] (u^(1)_e o ... o u^(N)_e)
  *   dV[m] = sum_e gy[m][e] u^(c)_r
  * (device, shaped like the parameters, overwritten).  The contraction is
- * the one of Eq (8); summation order is fixed (deterministic).
- * Asynchronous.                                                            */
+ * the one of Eq (8); summation order is fixed (deterministic): every row's
+ * contributions are summed in the bound item order, or, on a plan bound
+ * without one, in the storage order (training entries, then each matrix's
+ * entries).  Such a plan builds those reduction structures on its first
+ * call, in the part of the bound workspace the det structures would use:
+ * that call synchronises `stream` and needs the workspace that
+ * s3_workspace_size reports (S3_ERR_WORKSPACE if a smaller one was bound,
+ * S3_ERR_UNSUPPORTED past its 32-bit limits).  Det epochs still need an
+ * item order.  Otherwise asynchronous.                                     */
 s3_status s3_backward(s3_plan *plan, const void *gx, const void *const *gy,
                       void *const *dU, void *dG, void *const *dV, void *stream);
 

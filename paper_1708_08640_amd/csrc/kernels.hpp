@@ -65,7 +65,7 @@ static __global__ void k_order_keys(const int32_t *__restrict__ order, int64_t n
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; t < n; t += stride) {
-        const int64_t id = order[t];
+        const int64_t id = order ? order[t] : t;  // null: the storage order
         int type = 0;
         if (id >= nX) {
             type = 1;

@@ -102,7 +102,11 @@ struct s3_plan {
     void *part = nullptr, *part_curv = nullptr;
     int64_t max_chunks = 0;
     void *rows_part = nullptr;  // piece sums of the long segments of one batch
-    bool det_ready = false;
+    bool det_ready = false;   // det structures built from the caller's item order
+    bool adj_ready = false;   // det structures built (from that order, or from the storage order)
+    void *ws_base = nullptr;  // the bound workspace
+    size_t ws_bytes = 0;
+    size_t det_carve_off = 0;  // where the det structures start in it
     // lock-free structures
     LockFreeState lf;
     // orthogonalisation: Gram partials, per mode R / R^-1 / running R, a core copy

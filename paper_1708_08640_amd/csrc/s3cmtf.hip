@@ -390,8 +390,9 @@ s3_status s3_workspace_size(const s3_plan *cp, int64_t x_nnz, int64_t t_nnz, con
         return fail(p, S3_ERR_UNSUPPORTED, "det batches of %lld items: per-batch scratch offsets or batch keys "
                     "exceed 32 bits", (long long)p->d.batch);
     size_t temp = 0;
-    *bytes = (p->tsize == 8) ? layout<double>(p, nullptr, x_nnz, t_nnz, y_nnz, true, &temp)
-                             : layout<float>(p, nullptr, x_nnz, t_nnz, y_nnz, true, &temp);
+    s3_plan scratch_plan = *p;  // measuring carves null pointers: keep a bound plan's own intact
+    *bytes = (p->tsize == 8) ? layout<double>(&scratch_plan, nullptr, x_nnz, t_nnz, y_nnz, true, &temp)
+                             : layout<float>(&scratch_plan, nullptr, x_nnz, t_nnz, y_nnz, true, &temp);
     return S3_OK;
 }
 
@@ -430,30 +431,16 @@ void carve_det_temps(Carver &c, DetTemps &t, int64_t n, int64_t nb, int M) {
     t.temp = c.take<char>(t.temp_bytes + 256);
 }
 
-// Carve the workspace.  Returns total bytes.  base == nullptr: measure only.
+// The det-mode structures (item order, reduction segments, per-batch
+// scratch) and, after them, the temporaries that build them.
 template <typename T>
-size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_t *y_nnz, bool with_order,
-              size_t *temp_bytes_out) {
-    Carver c(base);
+void carve_det(s3_plan *p, Carver &c, int64_t x_nnz, const int64_t *y_nnz, size_t *temp_bytes_out) {
     const int N = p->N, M = p->M;
-    for (int n = 0; n < N; ++n) p->cnt[n] = c.take<int32_t>((size_t)p->d.dims[n]);
-    for (int m = 0; m < M; ++m) p->cntV[m] = c.take<int32_t>((size_t)p->d.mat_cols[m]);
-    p->Gp = c.take<T>((size_t)p->KP);
-    p->mx_g = c.take<char>((size_t)32 * 1024);  // the largest matrix-core operand layout (FP32, 4,096 values x 2)
-    p->flag = c.take<int32_t>(16);
-    p->n_red = std::max<int64_t>({(int64_t)2 * kReduceBlocks, sq_blocks(x_nnz), sq_blocks(t_nnz)});
-    p->red = c.take<double>((size_t)p->n_red);
     int64_t n_items = x_nnz;
     for (int m = 0; m < M; ++m) n_items += y_nnz[m];
     const int64_t B = p->d.batch;
     const int64_t nb = (n_items + B - 1) / B;
-    // lock-free structures
-    lockfree_layout<T>(p->lf, c, N, M, p->d, x_nnz, y_nnz, p->KP, p->JP);
-    // orthogonalisation
-    p->qr_part = c.take<double>((size_t)kQrBlocks * kQrJ * kQrJ);
-    p->qr_R = c.take<double>((size_t)N * 3 * kQrJ * kQrJ);
-    p->qr_G = c.take<T>((size_t)p->K);
-    if (with_order) {
+    {
         p->sorted_ids = c.take<int32_t>((size_t)n_items);
         p->bidx = c.take<int32_t>((size_t)N * n_items);
         p->bval = c.take<T>((size_t)n_items);
@@ -503,8 +490,32 @@ size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_
         carve_det_temps(c, tmp, n_items, nb, M);
         if (temp_bytes_out) *temp_bytes_out = c.off - t0;
     }
+}
+
+// Carve the workspace.  Returns total bytes.  base == nullptr: measure only.
+template <typename T>
+size_t layout(s3_plan *p, void *base, int64_t x_nnz, int64_t t_nnz, const int64_t *y_nnz, bool with_order,
+              size_t *temp_bytes_out) {
+    Carver c(base);
+    const int N = p->N, M = p->M;
+    for (int n = 0; n < N; ++n) p->cnt[n] = c.take<int32_t>((size_t)p->d.dims[n]);
+    for (int m = 0; m < M; ++m) p->cntV[m] = c.take<int32_t>((size_t)p->d.mat_cols[m]);
+    p->Gp = c.take<T>((size_t)p->KP);
+    p->mx_g = c.take<char>((size_t)32 * 1024);  // the largest matrix-core operand layout (FP32, 4,096 values x 2)
+    p->flag = c.take<int32_t>(16);
+    p->n_red = std::max<int64_t>({(int64_t)2 * kReduceBlocks, sq_blocks(x_nnz), sq_blocks(t_nnz)});
+    p->red = c.take<double>((size_t)p->n_red);
+    // lock-free structures
+    lockfree_layout<T>(p->lf, c, N, M, p->d, x_nnz, y_nnz, p->KP, p->JP);
+    // orthogonalisation
+    p->qr_part = c.take<double>((size_t)kQrBlocks * kQrJ * kQrJ);
+    p->qr_R = c.take<double>((size_t)N * 3 * kQrJ * kQrJ);
+    p->qr_G = c.take<T>((size_t)p->K);
+    p->det_carve_off = c.off;  // the det structures come last: an adjoint may carve them after bind
+    if (with_order) carve_det<T>(p, c, x_nnz, y_nnz, temp_bytes_out);
     return c.off + 256;
 }
+
 
 template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_t st) {
     const int N = p->N, M = p->M;
@@ -665,7 +676,35 @@ template <typename T> s3_status build_det(s3_plan *p, char *tmp_base, hipStream_
         HIPCHK(p, hipMemcpyAsync(G.pc1, q1.data(), sizeof(int64_t) * q1.size(), hipMemcpyHostToDevice, st));
         HIPCHK(p, hipStreamSynchronize(st));
     }
-    p->det_ready = true;
+    return S3_OK;
+}
+
+// The det structures from the storage order (training entries, then each
+// matrix's entries), for an adjoint on a plan bound without an item order.
+template <typename T> s3_status build_adjoint_order(s3_plan *p, hipStream_t st) {
+    if (!det_fits_32bit(p, p->nX, p->y_nnz))
+        return fail(p, S3_ERR_UNSUPPORTED, "adjoint batches of %lld items: per-batch scratch offsets or batch "
+                    "keys exceed 32 bits", (long long)p->d.batch);
+    size_t temp_bytes = 0;
+    {
+        s3_plan measure = *p;
+        Carver c(nullptr);
+        c.off = p->det_carve_off;
+        carve_det<T>(&measure, c, p->nX, p->y_nnz, &temp_bytes);
+        if (c.off + 256 > p->ws_bytes)
+            return fail(p, S3_ERR_WORKSPACE, "the adjoint needs a workspace of %zu bytes, %zu bound",
+                        c.off + 256, p->ws_bytes);
+    }
+    Carver c(p->ws_base);
+    c.off = p->det_carve_off;
+    carve_det<T>(p, c, p->nX, p->y_nnz, nullptr);
+    char *tmp = (char *)p->ws_base + (c.off - temp_bytes);  // the temporaries close the carve
+    const int32_t *saved = p->b.order;
+    p->b.order = nullptr;
+    s3_status s = build_det<T>(p, tmp, st);
+    p->b.order = saved;
+    if (s != S3_OK) return s;
+    p->adj_ready = true;
     return S3_OK;
 }
 
@@ -689,6 +728,8 @@ template <typename T> s3_status bind_impl(s3_plan *p, const s3_buffers *buf, voi
         if (s != S3_OK) return s;
     }
     p->b = *buf;
+    p->ws_base = ws;
+    p->ws_bytes = ws_bytes;
     p->nX = buf->x_nnz;
     p->nT = buf->t_nnz;
     int64_t n_items = p->nX;
@@ -734,11 +775,13 @@ template <typename T> s3_status bind_impl(s3_plan *p, const s3_buffers *buf, voi
         row_counts(buf->y_col[m], y_nnz[m], p->d.mat_cols[m], p->cntV[m], st);
     }
     p->det_ready = false;
+    p->adj_ready = false;
     if (with_order) {
         // temporaries sit at the end of the carved layout
         char *tmp = (char *)ws + (need - 256 - temp_bytes);  // the offset layout() measured from
         s3_status s = build_det<T>(p, tmp, st);
         if (s != S3_OK) return s;
+        p->det_ready = p->adj_ready = true;
     }
     s3_status s = lockfree_build<T>(p->lf, p->d, buf, p->cnt, p->cntV, p->nX, y_nnz, st, p->err);
     if (s != S3_OK) return s;
@@ -1003,13 +1046,17 @@ s3_status s3_predict_matrix(s3_plan *p, int32_t m, const int32_t *row, const int
 s3_status s3_backward(s3_plan *p, const void *gx, const void *const *gy, void *const *dU, void *dG,
                       void *const *dV, void *stream) {
     if (!p || !dU || !dG || (p->M > 0 && !dV)) return S3_ERR_INVALID_ARG;
-    if (!p->bound || !p->det_ready) return fail(p, S3_ERR_STATE, "s3_backward needs s3_bind with an item order");
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_backward before s3_bind");
     for (int n = 0; n < p->N; ++n)
         if (!dU[n]) return S3_ERR_INVALID_ARG;
     for (int m = 0; m < p->M; ++m)
         if (!dV[m]) return S3_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = p->tsize == 8;
+    if (!p->adj_ready) {
+        s3_status s = f64 ? build_adjoint_order<double>(p, st) : build_adjoint_order<float>(p, st);
+        if (s != S3_OK) return s;
+    }
     for (int n = 0; n < p->N; ++n)
         f64 ? fill<double>(dU[n], p->d.dims[n] * p->d.rank[n], 0.0, st) : fill<float>(dU[n], p->d.dims[n] * p->d.rank[n], 0.0, st);
     f64 ? fill<double>(dG, p->K, 0.0, st) : fill<float>(dG, p->K, 0.0, st);

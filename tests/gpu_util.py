@@ -18,7 +18,7 @@ def rounded_problem(p, dtype):
 
 
 def setup(name, dtype="f64", batch=512, damping=False, order_seed=123, round_items=65536, contraction="reuse",
-          core="tucker", **over):
+          core="tucker", with_order=True, **over):
     from paper_1708_08640_amd import S3Plan
     cfg = get_config(name, **over)
     p = rounded_problem(make_problem(cfg), dtype)
@@ -29,7 +29,8 @@ def setup(name, dtype="f64", batch=512, damping=False, order_seed=123, round_ite
         r = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
         U, G, V = [r(u) for u in U], r(G), [r(v) for v in V]
     order = item_order(p.n_items, order_seed, 0)
-    plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=batch, order=order, damping=damping,
+    plan = S3Plan.from_problem(p, (U, G, V), dtype=dtype, batch=batch, order=order if with_order else None,
+                               damping=damping,
                                round_items=round_items, seed=order_seed, contraction=contraction, core=core)
     ref = oracle.Params.from_arrays(U, G, V, [s.mode for s in cfg.matrices], cp=(core == "cp"))
     return cfg, p, plan, ref, order
