@@ -155,15 +155,16 @@ def zipf_ranks(rng: np.random.Generator, I: int, s: float, n: int) -> np.ndarray
     cdf = _zipf_cdf(int(I), float(s))
     u = rng.random(n)
     # inverse CDF, looked up in chunks by the worker threads
-    chunks = np.array_split(np.arange(n), max(1, min(4 * _THREADS, n // 65536 + 1)))
+    nch = max(1, min(4 * _THREADS, n // 65536 + 1))
+    edges = [n * k // nch for k in range(nch + 1)]
     r = np.empty(n, dtype=np.int64)
 
-    def look(ix):
-        if ix.size:
-            r[ix[0]:ix[-1] + 1] = np.searchsorted(cdf, u[ix[0]:ix[-1] + 1], side="right")
+    def look(k):
+        a, b = edges[k], edges[k + 1]
+        np.minimum(np.searchsorted(cdf, u[a:b], side="right"), I - 1, out=r[a:b])
 
-    _map(look, chunks)
-    return np.minimum(r, I - 1)
+    _map(look, range(nch))
+    return r
 
 
 def _draw_ranks(rng, I, law, n):
@@ -283,7 +284,9 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) 
     need = n
     for _ in range(max_rounds):
         c = draw(need)
-        keys = (c * strides[:, None]).sum(axis=0)
+        keys = c[-1].copy()
+        for d in range(len(dims) - 1):
+            keys += c[d] * strides[d]
         pos = fresh(keys)
         kept.append(c[:, pos])
         n_kept += pos.size
