@@ -174,7 +174,7 @@ def _draw_ranks(rng, I, law, n):
 
 
 def _mode_perm(seed: int, mode_tag: int, I: int) -> np.ndarray:
-    return _rng(seed, _S_PERM, mode_tag).permutation(I).astype(np.int64)
+    return _rng(seed, _S_PERM, mode_tag).permutation(I).astype(np.int32)
 
 
 def _draw_values(rng, law, n):
@@ -261,7 +261,7 @@ def _fresh_positions_map(keys: np.ndarray, seen: np.ndarray) -> np.ndarray:
 
 
 def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) -> np.ndarray:
-    """Draw n distinct coordinate tuples; draw(k) returns int64 [len(dims), k].
+    """Draw n distinct coordinate tuples; draw(k) returns int32 [len(dims), k].
 
     Duplicates of an already-kept coordinate are discarded and redrawn, so the
     result is a set, in first-drawn order.
@@ -284,9 +284,9 @@ def _distinct_coords(draw, dims: Sequence[int], n: int, max_rounds: int = 2000) 
     need = n
     for _ in range(max_rounds):
         c = draw(need)
-        keys = c[-1].copy()
+        keys = c[-1].astype(np.int64)
         for d in range(len(dims) - 1):
-            keys += c[d] * strides[d]
+            keys += c[d] * strides[d]  # int32 times an int64 scalar: int64
         pos = fresh(keys)
         kept.append(c[:, pos])
         n_kept += pos.size
@@ -304,7 +304,7 @@ def _tensor(cfg: Config):
     rng = _rng(cfg.seed_data, _S_IDX)
 
     def draw(k):
-        out = np.empty((N, k), dtype=np.int64)
+        out = np.empty((N, k), dtype=np.int32)
         for n in range(N):
             out[n] = perms[n][_draw_ranks(rng, cfg.dims[n], cfg.index_law[n], k)]
         return out
@@ -329,7 +329,7 @@ def _matrix(cfg: Config, m: int, spec: MatrixSpec, row_perm: np.ndarray):
     vrng = _rng(cfg.seed_data, _S_MAT + m, 1)
     if spec.nnz == I * K:  # fully observed: enumerate
         r, c = np.meshgrid(np.arange(I), np.arange(K), indexing="ij")
-        coords = np.stack([r.ravel(), c.ravel()]).astype(np.int64)
+        coords = np.stack([r.ravel(), c.ravel()]).astype(np.int32)
         order = rng.permutation(coords.shape[1])
         coords = coords[:, order]
     else:
@@ -368,13 +368,15 @@ def _make_problem(cfg: Config) -> Problem:
     is_test[sp[:n_test]] = True
     test_sel = np.flatnonzero(is_test)   # increasing, as a sort of sp[:n_test]
     train_sel = np.flatnonzero(~is_test)
-    p = Problem(
-        cfg=cfg,
-        train_idx=np.ascontiguousarray(coords[:, train_sel].astype(np.int32)),
-        train_val=np.ascontiguousarray(vals[train_sel]),
-        test_idx=np.ascontiguousarray(coords[:, test_sel].astype(np.int32)),
-        test_val=np.ascontiguousarray(vals[test_sel]),
-    )
+    N = coords.shape[0]
+    train_idx = np.empty((N, train_sel.size), dtype=np.int32)
+    test_idx = np.empty((N, test_sel.size), dtype=np.int32)
+    train_val = np.empty(train_sel.size, dtype=vals.dtype)
+    test_val = np.empty(test_sel.size, dtype=vals.dtype)
+    jobs = [(coords[d], sel, dst[d]) for d in range(N) for sel, dst in ((train_sel, train_idx), (test_sel, test_idx))]
+    jobs += [(vals, train_sel, train_val), (vals, test_sel, test_val)]
+    _map(lambda j: np.take(j[0], j[1], out=j[2]), jobs)  # the split's gathers, by the worker threads
+    p = Problem(cfg=cfg, train_idx=train_idx, train_val=train_val, test_idx=test_idx, test_val=test_val)
     for m, spec in enumerate(cfg.matrices):
         r, c, v = _matrix(cfg, m, spec, perms[spec.mode])
         p.mat_row.append(r)
