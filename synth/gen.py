@@ -150,9 +150,45 @@ def _map(fn, items):
     return list(_pool.map(fn, items))
 
 
+_GUIDE = 1 << 20  # cells of the inverse-CDF guide table
+
+
+@functools.lru_cache(maxsize=16)
+def _zipf_guide(I: int, s: float) -> np.ndarray:
+    """guide[g] = #{i : cdf[i] <= g / _GUIDE} for g = 0 .. _GUIDE (exact
+    fractions: _GUIDE is a power of two)."""
+    cdf = _zipf_cdf(I, s)
+    g = np.searchsorted(cdf, np.arange(_GUIDE + 1, dtype=np.float64) / _GUIDE, side="right")
+    g.setflags(write=False)
+    return g
+
+
+def _inverse_cdf(cdf: np.ndarray, guide: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """#{i : cdf[i] <= u} per element of u in [0, 1), the result of
+    searchsorted(cdf, u, side="right"), found from the guide cell of u and a
+    search between its bounds (the count is monotone in u, so it lies in
+    [guide[g], guide[g + 1]] for g = floor(u * _GUIDE))."""
+    g = (u * _GUIDE).astype(np.int64)
+    r = guide[g]
+    hi = guide[g + 1]
+    amb = np.flatnonzero(r < hi)
+    lo, hi, uu = r[amb], hi[amb], u[amb]
+    while amb.size:
+        mid = (lo + hi) >> 1
+        le = cdf[mid] <= uu           # mid < hi <= len(cdf)
+        lo = np.where(le, mid + 1, lo)
+        hi = np.where(le, hi, mid)
+        open_ = lo < hi
+        if not open_.all():
+            r[amb[~open_]] = lo[~open_]
+            amb, lo, hi, uu = amb[open_], lo[open_], hi[open_], uu[open_]
+    return r
+
+
 def zipf_ranks(rng: np.random.Generator, I: int, s: float, n: int) -> np.ndarray:
     """Draw n ranks in [0, I) with P(r) proportional to (r+1)^-s (bounded Zipf)."""
     cdf = _zipf_cdf(int(I), float(s))
+    guide = _zipf_guide(int(I), float(s))
     u = rng.random(n)
     # inverse CDF, looked up in chunks by the worker threads
     nch = max(1, min(4 * _THREADS, n // 65536 + 1))
@@ -161,7 +197,7 @@ def zipf_ranks(rng: np.random.Generator, I: int, s: float, n: int) -> np.ndarray
 
     def look(k):
         a, b = edges[k], edges[k + 1]
-        np.minimum(np.searchsorted(cdf, u[a:b], side="right"), I - 1, out=r[a:b])
+        np.minimum(_inverse_cdf(cdf, guide, u[a:b]), I - 1, out=r[a:b])
 
     _map(look, range(nch))
     return r
