@@ -95,11 +95,15 @@ def test_calls_before_bind_are_state_errors():
     assert lib.s3_loss(h, out, None) == -7
     assert lib.s3_rmse(h, out, None) == -7
     assert lib.s3_det_batches(h, 0, 1, 0.01, None) == -7
+    fake = (C.c_void_p * 4)(8, 8, 8, 8)  # never dereferenced: the state check comes first
+    assert lib.s3_backward(h, C.c_void_p(8), None, fake, C.c_void_p(8), fake, None) == -7
     buf = C.create_string_buffer(256)
     assert lib.s3_last_error(h, buf, 256) == 0 and b"bind" in buf.value
     y = (C.c_int64 * 1)(100)
     sz = C.c_size_t()
     assert lib.s3_workspace_size(h, 1000, 100, y, C.byref(sz)) == 0 and sz.value > 0
+    again = C.c_size_t()
+    assert lib.s3_workspace_size(h, 1000, 100, y, C.byref(again)) == 0 and again.value == sz.value
     assert lib.s3_workspace_size(h, 0, 100, y, C.byref(sz)) == -1
     assert lib.s3_plan_destroy(h) == 0
 
