@@ -50,14 +50,27 @@ def lib_path() -> str:
     return _LIB
 
 
+def _sanitized() -> bool:
+    # S3_ORACLE_SANITIZE=1: load a build instrumented with AddressSanitizer and
+    # UndefinedBehaviorSanitizer (the process must preload gcc's libasan)
+    return os.environ.get("S3_ORACLE_SANITIZE") == "1"
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-pthread",
+    """Compile the oracle with gcc (plain -O2, no fast-math; with
+    S3_ORACLE_SANITIZE=1 a separate ASan/UBSan build, stopping at the first
+    report)."""
+    lib, flags = _LIB, ["-O2"]
+    if _sanitized():
+        lib = os.path.join(_HERE, "libs3oracle_san.so")
+        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=all"]
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *flags, "-std=c11", "-fPIC", "-shared", "-Wall", "-pthread",
                                "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
@@ -66,8 +79,7 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
-        build()
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(build())
         M, T, Y, Cn, H = (C.POINTER(_Model), C.POINTER(_Tensor), C.POINTER(_Matrix),
                           C.POINTER(_Counts), C.POINTER(_Hyper))
         lib.or_counts_build.argtypes = [M, T, C.c_int32, Y, Cn]

@@ -37,14 +37,33 @@ def sources():
         os.path.join(INCLUDE, "s3cmtf.h")]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 and link the in-tree shared library."""
+# host code of the entry points (s3cmtf.hip) under AddressSanitizer and
+# UndefinedBehaviorSanitizer; device code is built as usual.  A process that
+# loads such a build must preload the compiler's shared ASan runtime.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def asan_runtime() -> str:
+    """Path of the shared ASan runtime of the compiler hipcc drives."""
+    clang = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
+    res = subprocess.run([clang, "-print-resource-dir"], capture_output=True, text=True, check=True)
+    return os.path.join(res.stdout.strip(), "lib", "linux", "libclang_rt.asan-x86_64.so")
+
+
+def build(verbose: bool = False, out: str = LIB, host_sanitize: bool = False) -> str:
+    """Compile every HIP source for gfx950 and link the shared library (the
+    in-tree one unless `out` names another path; `host_sanitize` instruments
+    the entry points' host code)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tag = "%d" % os.getpid()
-    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".o.tmp" + tag) for s in SOURCES]
+    odir = CSRC if out == LIB else os.path.dirname(os.path.abspath(out))
+    objs = [os.path.join(odir, os.path.splitext(s)[0] + ".o.tmp" + tag) for s in SOURCES]
 
     def compile_one(i):
-        cmd = [hipcc, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", "-o", objs[i], os.path.join(CSRC, SOURCES[i])]
+        extra = HOST_SANITIZE if host_sanitize and SOURCES[i] == "s3cmtf.hip" else []
+        cmd = [hipcc, *FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", "-o", objs[i],
+               os.path.join(CSRC, SOURCES[i])]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
@@ -53,17 +72,19 @@ def build(verbose: bool = False) -> str:
     try:
         with ThreadPoolExecutor(jobs) as ex:
             list(ex.map(compile_one, range(len(SOURCES))))
-        tmp = LIB + ".tmp" + tag
-        cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+        tmp = out + ".tmp" + tag
+        link = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-shared-libsan"] if host_sanitize else []
+        cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *link, "-o", tmp, *objs]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        os.replace(tmp, LIB)
+        os.replace(tmp, out)
     finally:
         for o in objs:
             if os.path.exists(o):
                 os.remove(o)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":
