@@ -53,6 +53,28 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+class EpochLog:
+    """One JSON line per epoch appended to a file (nothing without a path):
+    workload, mode, operand type, phase (warmup, timed, quality), epoch, the
+    epoch's learning rate eta0 / (1 + mu e), its wall time and update rate,
+    and where they are evaluated (not inside the timed region) the loss terms
+    f, f_t, f_m of Eq (7) and the held-out RMSE."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def write(self, cfg, mode, dtype, phase, epoch, ms, updates, loss=None, rmse=None):
+        if not self.path:
+            return
+        rec = {"workload": cfg.name, "mode": mode, "dtype": dtype, "phase": phase, "epoch": epoch + 1,
+               "eta": cfg.eta0 / (1.0 + cfg.mu * epoch), "epoch_ms": ms,
+               "updates_per_s": updates / (ms / 1e3) if ms > 0 else None,
+               "f": None if loss is None else loss[0], "f_t": None if loss is None else loss[1],
+               "f_m": None if loss is None else loss[2], "heldout_rmse": rmse}
+        with open(self.path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+
+
 def tensor_entry_flops(ranks):
     """Algorithmic FP operations of one tensor entry: 4K for the single-pass
     contraction (x~ and every leave-one-out vector), 2K for its share of the
@@ -275,10 +297,15 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     torch.cuda.synchronize()
     rmse0 = plan.rmse()
     log(f"bound; initial held-out RMSE {rmse0:.4f}")
+    elog = EpochLog(args.epoch_log)
     for e in range(warmup):
+        te = time.perf_counter()
         plan.epoch(e, mode)
         torch.cuda.synchronize()
-        log(f"warmup epoch {e}: RMSE {plan.rmse():.4f}")
+        wms = (time.perf_counter() - te) * 1e3
+        r = plan.rmse()
+        log(f"warmup epoch {e}: RMSE {r:.4f}")
+        elog.write(cfg, mode, dtype, "warmup", e, wms, n_updates, plan.loss() if elog.path else None, r)
 
     plan.set_profiling(True)
     kernel_ms, launches, epoch_ms = 0.0, 0, []
@@ -291,6 +318,7 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
         kernel_ms += ms
         launches += n
         epoch_ms.append((time.perf_counter() - te) * 1e3)
+        elog.write(cfg, mode, dtype, "timed", e, epoch_ms[-1], n_updates)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plan.set_profiling(False)
@@ -306,8 +334,12 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
             dst.copy_(torch.as_tensor(np.asarray(src), dtype=dst.dtype))
     traj = []
     for e in range(estar):
+        te = time.perf_counter()
         plan.epoch(e, mode)
         traj.append(plan.rmse())
+        if elog.path:
+            elog.write(cfg, mode, dtype, "quality", e, (time.perf_counter() - te) * 1e3, n_updates, plan.loss(),
+                       traj[-1])
     target, sgd_mean, det_mean = oracle_target(config, estar) if args.scale == 1.0 else (None, None, None)
     log(f"quality pass: RMSE after epochs 1..{estar}: {' '.join(f'{v:.4f}' for v in traj)}; target "
         f"{target if target is None else round(target, 4)}")
@@ -409,6 +441,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--epoch-log", default=None, metavar="PATH",
+                    help="append one JSON line per epoch (warmup, timed, quality pass) to PATH")
     ap.add_argument("--scaling", choices=["dims", "nnz"], default=None,
                     help="data-scalability sweep instead of the benchmark: epoch time of uniform 3-way tensors "
                          "against the dimensionality I (1M entries) or the entry count (I = 10K); one JSON line "

@@ -56,3 +56,21 @@ def test_traffic_lookup_follows_the_kernel_code():
         expect = int(fields["traffic_bytes_per_launch"]) if stored == h else None
         assert bench.profiled_traffic(kernel, workload) == expect
     assert bench.profiled_traffic("k_lf_tensor_mx", "no_such_workload") is None
+
+
+def test_epoch_log_lines(tmp_path):
+    from synth import get_config
+    cfg = get_config("cfg2")
+    bench.EpochLog(None).write(cfg, "lockfree", "f32", "timed", 0, 2.0, 100)  # no path: nothing
+    path = tmp_path / "epochs.jsonl"
+    log = bench.EpochLog(str(path))
+    log.write(cfg, "lockfree", "f32", "warmup", 0, 4.0, 1000, (3.0, 2.0, 1.0), 1.5)
+    log.write(cfg, "lockfree", "f32", "timed", 2, 2.0, 1000)
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(recs) == 2
+    a, b = recs
+    assert a["epoch"] == 1 and a["eta"] == cfg.eta0 and a["updates_per_s"] == 250000.0
+    assert (a["f"], a["f_t"], a["f_m"], a["heldout_rmse"]) == (3.0, 2.0, 1.0, 1.5)
+    # the rate of epoch e (0-based) is eta0 / (1 + mu e)
+    assert b["epoch"] == 3 and abs(b["eta"] - cfg.eta0 / (1 + 2 * cfg.mu)) < 1e-15
+    assert b["f"] is None and b["heldout_rmse"] is None and b["phase"] == "timed"
