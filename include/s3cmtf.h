@@ -295,6 +295,20 @@ s3_status s3_backward(s3_plan *plan, const void *gx, const void *const *gy,
 s3_status s3_export(s3_plan *plan, int32_t which, int32_t index, double *host_dst,
                     size_t bytes, void *stream);
 
+/* The inverse of s3_export, for checkpoint and resume: copy a parameter from
+ * host memory (float64, the caller's, row-major as exported) into the bound
+ * plan's parameter buffer; which/index/bytes as for s3_export.  FP32 and
+ * BF16-operand plans store each value rounded to the nearest FP32 (their
+ * masters).  A value that is not finite gives S3_ERR_NONFINITE and nothing
+ * is written.  Every later call reads the new values (derived copies of the
+ * core are rebuilt at the start of each call).  The learning rate depends
+ * only on the epoch index passed to s3_epoch (Algorithm 1's schedule), so a
+ * det run resumed by importing every parameter exported after epoch e and
+ * continuing with epoch e + 1 reproduces the uninterrupted run bitwise.
+ * Synchronous.                                                            */
+s3_status s3_import(s3_plan *plan, int32_t which, int32_t index, const double *host_src,
+                    size_t bytes, void *stream);
+
 /* Orthogonalise the bound parameters in place (Algorithm 1, closing step):
  * every factor U^(n) = Q R becomes Q (orthonormal columns), the core becomes
  * G x_n R for every mode n, and every coupled V_m becomes V_m R^(c_m)T, so

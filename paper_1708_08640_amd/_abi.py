@@ -29,7 +29,7 @@ S3_CORE_TUCKER, S3_CORE_CP = 0, 1
 EXPORTS = [
     "s3_status_string", "s3_last_error", "s3_plan_create", "s3_plan_destroy", "s3_workspace_size",
     "s3_bind", "s3_epoch", "s3_det_batches", "s3_loss", "s3_rmse", "s3_predict", "s3_predict_noalloc", "s3_predict_matrix",
-    "s3_backward", "s3_export", "s3_orthogonalize", "s3_init_params", "s3_set_profiling",
+    "s3_backward", "s3_export", "s3_import", "s3_orthogonalize", "s3_init_params", "s3_set_profiling",
     "s3_last_epoch_profile",
 ]
 
@@ -93,6 +93,7 @@ def load() -> C.CDLL:
         "s3_predict_matrix": ([vp, i32, vp, vp, i64, vp, vp], i32),
         "s3_backward": ([vp, vp, C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(vp), vp], i32),
         "s3_export": ([vp, i32, i32, C.POINTER(dbl), C.c_size_t, vp], i32),
+        "s3_import": ([vp, i32, i32, C.POINTER(dbl), C.c_size_t, vp], i32),
         "s3_orthogonalize": ([vp, vp], i32),
         "s3_init_params": ([vp, C.c_uint64, dbl, vp], i32),
         "s3_set_profiling": ([vp, i32], i32),

@@ -1075,23 +1075,37 @@ s3_status s3_backward(s3_plan *p, const void *gx, const void *const *gy, void *c
     return S3_OK;
 }
 
-s3_status s3_export(s3_plan *p, int32_t which, int32_t index, double *host_dst, size_t bytes, void *stream) {
-    if (!p || !host_dst) return S3_ERR_INVALID_ARG;
-    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_export before s3_bind");
-    const void *src = nullptr;
-    int64_t count = 0;
+}  // extern "C"
+
+namespace {
+// the bound parameter buffer (which = 0: U[index], 1: G, 2: V[index]) and
+// its element count, or an error when no such parameter exists
+s3_status param_slot(s3_plan *p, int32_t which, int32_t index, void **ptr, int64_t *count) {
     if (which == 0 && index >= 0 && index < p->N) {
-        src = p->b.U[index];
-        count = p->d.dims[index] * p->d.rank[index];
+        *ptr = p->b.U[index];
+        *count = p->d.dims[index] * p->d.rank[index];
     } else if (which == 1) {
-        src = p->b.G;
-        count = p->K;
+        *ptr = p->b.G;
+        *count = p->K;
     } else if (which == 2 && index >= 0 && index < p->M) {
-        src = p->b.V[index];
-        count = p->d.mat_cols[index] * p->d.rank[p->d.mat_mode[index]];
+        *ptr = p->b.V[index];
+        *count = p->d.mat_cols[index] * p->d.rank[p->d.mat_mode[index]];
     } else {
         return fail(p, S3_ERR_INVALID_ARG, "unknown parameter (%d, %d)", which, index);
     }
+    return S3_OK;
+}
+}  // namespace
+
+extern "C" {
+
+s3_status s3_export(s3_plan *p, int32_t which, int32_t index, double *host_dst, size_t bytes, void *stream) {
+    if (!p || !host_dst) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_export before s3_bind");
+    void *src = nullptr;
+    int64_t count = 0;
+    s3_status s = param_slot(p, which, index, &src, &count);
+    if (s != S3_OK) return s;
     if (bytes != (size_t)count * sizeof(double))
         return fail(p, S3_ERR_INVALID_ARG, "export needs %lld bytes", (long long)(count * 8));
     hipStream_t st = (hipStream_t)stream;
@@ -1103,6 +1117,33 @@ s3_status s3_export(s3_plan *p, int32_t which, int32_t index, double *host_dst, 
         HIPCHK(p, hipMemcpyAsync(tmp.data(), src, sizeof(float) * count, hipMemcpyDeviceToHost, st));
         HIPCHK(p, hipStreamSynchronize(st));
         for (int64_t i = 0; i < count; ++i) host_dst[i] = (double)tmp[(size_t)i];
+    }
+    return S3_OK;
+}
+
+s3_status s3_import(s3_plan *p, int32_t which, int32_t index, const double *host_src, size_t bytes,
+                    void *stream) {
+    if (!p || !host_src) return S3_ERR_INVALID_ARG;
+    if (!p->bound) return fail(p, S3_ERR_STATE, "s3_import before s3_bind");
+    void *dst = nullptr;
+    int64_t count = 0;
+    s3_status s = param_slot(p, which, index, &dst, &count);
+    if (s != S3_OK) return s;
+    if (bytes != (size_t)count * sizeof(double))
+        return fail(p, S3_ERR_INVALID_ARG, "import needs %lld bytes", (long long)(count * 8));
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(host_src[i]))
+            return fail(p, S3_ERR_NONFINITE, "import: value %lld is not finite", (long long)i);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->tsize == 8) {
+        HIPCHK(p, hipMemcpyAsync(dst, host_src, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(p, hipStreamSynchronize(st));
+    } else {
+        // round to nearest FP32 (the masters of FP32 and BF16-operand plans)
+        std::vector<float> tmp((size_t)count);
+        for (int64_t i = 0; i < count; ++i) tmp[(size_t)i] = (float)host_src[i];
+        HIPCHK(p, hipMemcpyAsync(dst, tmp.data(), sizeof(float) * count, hipMemcpyHostToDevice, st));
+        HIPCHK(p, hipStreamSynchronize(st));
     }
     return S3_OK;
 }

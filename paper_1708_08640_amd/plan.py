@@ -226,6 +226,14 @@ class S3Plan:
                                  out.nbytes, _stream()), self.h)
         return out
 
+    def import_(self, which: str, index: int, values) -> None:
+        """Write host float64 values into parameter U[index], G or V[index]
+        (the inverse of export)."""
+        code = {"U": 0, "G": 1, "V": 2}[which]
+        a = np.ascontiguousarray(values, dtype=np.float64)
+        check(self.lib.s3_import(self.h, code, int(index), a.ctypes.data_as(C.POINTER(C.c_double)),
+                                 a.nbytes, _stream()), self.h)
+
     def orthogonalize(self) -> None:
         """Algorithm 1's closing step on the device: U <- Q, G <- G x_n R,
         V <- V R^T (predictions unchanged)."""

@@ -180,3 +180,15 @@ def test_det_offsets_beyond_32_bits_are_rejected():
                 assert lib.s3_bind(h, C.byref(b), C.c_void_p(fake), 1 << 40, None) == -3
         finally:
             lib.s3_plan_destroy(h)
+
+
+def test_import_before_bind_is_a_state_error():
+    _abi, lib = _lib()
+    plan = C.c_void_p()
+    assert lib.s3_plan_create(C.byref(_desc(_abi)), C.byref(plan)) == _abi.S3_OK
+    try:
+        buf = (C.c_double * 4)()
+        assert lib.s3_import(plan, 1, 0, buf, C.sizeof(buf), None) == _abi.S3_ERR_STATE
+        assert lib.s3_import(plan, 1, 0, None, 0, None) == _abi.S3_ERR_INVALID_ARG
+    finally:
+        lib.s3_plan_destroy(plan)

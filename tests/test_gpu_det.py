@@ -158,3 +158,42 @@ def test_resume_from_exported_parameters_is_exact():
     for a, b in zip(straight[0] + [straight[1]] + straight[2],
                     resumed.params_numpy()[0] + [resumed.params_numpy()[1]] + resumed.params_numpy()[2]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,dtype,batch,contraction", [("cfg1", "f64", 500, "reuse"),
+                                                           ("cfg1", "f32", 333, "reuse"),
+                                                           ("cfg5_slice", "bf16", 4096, "matrix")])
+def test_resume_through_import_is_exact(name, dtype, batch, contraction):
+    """s3_import writes exported parameters back into a bound plan: a plan
+    that has run two epochs, given the parameters exported after epoch 0 and
+    run again from epoch 1, ends bitwise where the uninterrupted run ended;
+    export after import returns the imported values exactly."""
+    from paper_1708_08640_amd._abi import S3Error
+    cfg, p, plan, ref, order = setup(name, dtype, batch, True, contraction=contraction)
+    plan.epoch(0, "det")
+    mid = plan.params_numpy()
+    plan.epoch(1, "det")
+    straight = plan.params_numpy()
+    for n, u in enumerate(mid[0]):
+        plan.import_("U", n, u)
+    plan.import_("G", 0, mid[1])
+    for m, v in enumerate(mid[2]):
+        plan.import_("V", m, v)
+    back = plan.params_numpy()
+    for a, b in zip(mid[0] + [mid[1]] + mid[2], back[0] + [back[1]] + back[2]):
+        assert np.array_equal(a, b)
+    plan.epoch(1, "det")
+    again = plan.params_numpy()
+    for a, b in zip(straight[0] + [straight[1]] + straight[2], again[0] + [again[1]] + again[2]):
+        assert np.array_equal(a, b)
+
+    # rejected imports leave the parameter as it was
+    bad = mid[0][0].copy()
+    bad[3, 0] = np.nan
+    with pytest.raises(S3Error):
+        plan.import_("U", 0, bad)
+    with pytest.raises(S3Error):
+        plan.import_("U", 0, mid[0][0][:-1])
+    with pytest.raises(S3Error):
+        plan.import_("V", len(mid[2]), mid[0][0])
+    assert np.array_equal(plan.export("U", 0), again[0][0])
