@@ -217,7 +217,10 @@ s3_status s3_workspace_size(const s3_plan *plan, int64_t x_nnz, int64_t t_nnz,
  * given, the fixed per-batch reduction order of det mode (S3_ERR_UNSUPPORTED,
  * before any device access, if it would overflow its 32-bit fields; see
  * s3_workspace_size).  S3_ERR_WORKSPACE if ws_bytes is too small.
- * Synchronises `stream`.                                                  */
+ * The plan keeps the buffers' addresses: they stay the caller's, must stay
+ * allocated until the plan is destroyed, and the index buffers must not
+ * change while bound (they are range-checked only here; the parameters are
+ * updated in place).  Synchronises `stream`.                              */
 s3_status s3_bind(s3_plan *plan, const s3_buffers *buf, void *d_ws, size_t ws_bytes,
                   void *stream);
 
