@@ -28,7 +28,9 @@ def _gcc_runtime(name):
 
 def _env(preload):
     env = dict(os.environ)
-    env.update(S3_ORACLE_SANITIZE="1", LD_PRELOAD=preload,
+    # the ASan runtime must come first; whatever is preloaded already stays
+    prior = env.get("LD_PRELOAD", "").strip()
+    env.update(S3_ORACLE_SANITIZE="1", LD_PRELOAD=preload + (":" + prior if prior else ""),
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=0:exitcode=86",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
     return env
