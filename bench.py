@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tensor+matrix nonzero updates/sec per epoch at fixed held-out RMSE, 1 GPU"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -399,9 +400,10 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     else:
         flops = (tensor_entry_flops(cfg.ranks) * p.n_train + mat_flops) * steps
         achieved = flops / secs / 1e12 if secs > 0 else None
+        vpeak = PEAK_FP64_VECTOR_TFLOPS if dtype == "f64" else PEAK_FP32_VECTOR_TFLOPS
         roofline = {"bound": "alu", "kernel": kname,
-                    "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                    "frac": (achieved / PEAK_FP32_VECTOR_TFLOPS) if achieved else None,
+                    "achieved": achieved, "peak": vpeak, "unit": "TFLOP/s",
+                    "frac": (achieved / vpeak) if achieved else None,
                     "traffic": traffic,
                     "flops_per_tensor_entry": tensor_entry_flops(cfg.ranks)}
     roofline.update({"launches": launches, "avg_launch_ms": kernel_ms / max(launches, 1),
@@ -412,8 +414,9 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
         # CP: O(NJ) flops per entry, so the bound is HBM: algorithmic bytes =
         # index + value stream and every touched row read and written once
         J = cfg.ranks[0]
-        t_bytes = 4 * cfg.order + 4 + 2 * 4 * J * cfg.order
-        m_bytes = 12 + 2 * 2 * 4 * J
+        es = 8 if dtype == "f64" else 4  # bytes per value and parameter
+        t_bytes = 4 * cfg.order + es + 2 * es * J * cfg.order
+        m_bytes = 8 + es + 2 * 2 * es * J
         nbytes = (t_bytes * p.n_train + m_bytes * (n_updates - p.n_train)) * steps
         gbs = nbytes / secs / 1e9 if secs > 0 else None
         roofline.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -451,9 +454,9 @@ def main():
     ap.add_argument("--contraction", default=None, choices=["reuse", "naive", "matrix"],
                     help="reuse: the single pass on the vector units; naive: without reuse of partial products "
                          "(ablation); matrix: the dense part on the matrix cores (default where it is built)")
-    ap.add_argument("--dtype", default=None, choices=["f32", "bf16"],
+    ap.add_argument("--dtype", default=None, choices=["f64", "f32", "bf16"],
                     help="bf16: FP32 master parameters, BF16 operands on the matrix cores (default with the "
-                         "matrix contraction)")
+                         "matrix contraction); f64: FP64 throughout, on the vector units")
     ap.add_argument("--no-f32-compare", action="store_true",
                     help="skip the FP32-operand run of the same workload that follows a BF16 headline")
     ap.add_argument("--no-det-compare", action="store_true",
@@ -507,11 +510,17 @@ def main():
         c = get_config(config)
         jp = max(c.ranks)
         built = (c.order == 4 and 5 <= jp <= 8) or (c.order == 3 and 13 <= jp <= 16)
-        ct = args.contraction or ("matrix" if (built and args.core == "tucker") else "reuse")
+        ct = args.contraction or ("matrix" if (built and args.core == "tucker" and args.dtype != "f64")
+                                  else "reuse")
         dt = args.dtype or ("bf16" if ct == "matrix" else "f32")
         return ct, dt
 
     ct, dt = defaults(args.config)
+    if dt == "f64" and args.mode == "lockfree":
+        # FP64 staging of a tile's rows alone exceeds the 64 KB LDS budget of
+        # the round kernel at 3-way rank 10 and 4-way rank 8
+        print("bench.py: FP64 runs in det mode only on these workloads (--mode det)", file=sys.stderr)
+        sys.exit(2)
     data = generate(args, args.config)
     head = run(args, data, args.config, ct, dt, args.mode, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
     cfg = head["cfg"]

@@ -27,6 +27,7 @@ CASES = [
     ("tiny3", "f64", 7, False),
     ("tiny4", "f64", 5, True),
     ("cfg1", "f32", 333, False),
+    ("cfg2_slice", "f64", 8192, True),  # FP64 at the 10M-entry workload's rank 10
     ("cfg2_slice", "f32", 8192, True),
     ("cfg2_slice", "f32", 4096, False),
     ("cfg5_slice", "f32", 4096, True),
