@@ -46,23 +46,24 @@ class _Hyper(C.Structure):
     _fields_ = [("lambda_reg", C.c_double), ("lambda_m", C.c_double)]
 
 
-def lib_path() -> str:
-    return _LIB
-
-
 def _sanitized() -> bool:
     # S3_ORACLE_SANITIZE=1: load a build instrumented with AddressSanitizer and
     # UndefinedBehaviorSanitizer (the process must preload gcc's libasan)
     return os.environ.get("S3_ORACLE_SANITIZE") == "1"
 
 
+def lib_path() -> str:
+    """The oracle library this process loads (the sanitized build when
+    S3_ORACLE_SANITIZE=1)."""
+    return os.path.join(_HERE, "libs3oracle_san.so") if _sanitized() else _LIB
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math; with
     S3_ORACLE_SANITIZE=1 a separate ASan/UBSan build, stopping at the first
     report)."""
-    lib, flags = _LIB, ["-O2"]
+    lib, flags = lib_path(), ["-O2"]
     if _sanitized():
-        lib = os.path.join(_HERE, "libs3oracle_san.so")
         flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                  "-fno-sanitize-recover=all"]
     if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
