@@ -254,8 +254,9 @@ s3_status s3_rmse(s3_plan *plan, double *out, void *stream);
 s3_status s3_predict(s3_plan *plan, const int32_t *idx, int64_t nnz, void *xhat,
                      void *stream);
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc; not code under HIP graph capture, since
+ * the index check synchronises the stream): the same
  * result as s3_predict, bitwise, with its working memory (the index-check
  * flag and the zero-padded core, at most 64 KiB) taken from a static array
  * in the library's device code instead of the plan's workspace.  Allocates
