@@ -93,6 +93,15 @@ def matrix_entry_flops(rank):
     return 10 * rank
 
 
+def cp_entry_bytes(order, J, dtype):
+    """Algorithmic HBM bytes of one entry with the CP core, as (tensor,
+    matrix): the index and value stream, and every factor row the entry
+    touches read and written once (values and parameters of 8 bytes in FP64,
+    4 otherwise)."""
+    es = 8 if dtype == "f64" else 4
+    return 4 * order + es + 2 * es * J * order, 8 + es + 2 * 2 * es * J
+
+
 def kernel_source_hash():
     """Hash of the kernel sources' code (comments and blank space removed, so
     that editing a comment does not orphan the committed counter summaries)."""
@@ -413,10 +422,7 @@ def run(args, data, config, contraction, dtype, mode, steps, warmup, cpu=False):
     if args.core == "cp":
         # CP: O(NJ) flops per entry, so the bound is HBM: algorithmic bytes =
         # index + value stream and every touched row read and written once
-        J = cfg.ranks[0]
-        es = 8 if dtype == "f64" else 4  # bytes per value and parameter
-        t_bytes = 4 * cfg.order + es + 2 * es * J * cfg.order
-        m_bytes = 8 + es + 2 * 2 * es * J
+        t_bytes, m_bytes = cp_entry_bytes(cfg.order, cfg.ranks[0], dtype)
         nbytes = (t_bytes * p.n_train + m_bytes * (n_updates - p.n_train)) * steps
         gbs = nbytes / secs / 1e9 if secs > 0 else None
         roofline.update({"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",

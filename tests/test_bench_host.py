@@ -74,3 +74,32 @@ def test_epoch_log_lines(tmp_path):
     # the rate of epoch e (0-based) is eta0 / (1 + mu e)
     assert b["epoch"] == 3 and abs(b["eta"] - cfg.eta0 / (1 + 2 * cfg.mu)) < 1e-15
     assert b["f"] is None and b["heldout_rmse"] is None and b["phase"] == "timed"
+
+
+def test_small_sweep_points_and_ratios(monkeypatch):
+    calls = []
+
+    def fake_point(I, nnz, round_items, hot_rows, seed, warmup=1, steps=2):
+        calls.append((I, nnz))
+        n_train = int(nnz * 0.9)
+        return {"I": I, "nnz_tensor_train": n_train, "nnz_matrix": nnz // 10,
+                "ms_per_epoch": 1.0 + I / 1e6 + nnz / 1e6, "updates_per_s": 1.0, "heldout_rmse": 3.3}
+
+    monkeypatch.setattr(bench, "scaling_point", fake_point)
+    import argparse
+    sw = bench.small_sweep(argparse.Namespace(round_items=None, hot_rows=64, seed=7))
+    assert calls == [(1_000, 1_000_000), (10_000, 1_000_000), (100_000, 1_000_000), (1_000_000, 1_000_000),
+                     (10_000, 100_000), (10_000, 10_000_000)]
+    # the 1M-entry point at I = 10^4 is shared by both sweeps
+    assert [p["nnz_tensor_train"] + p["nnz_matrix"] for p in sw["nnz"]] == [100_000, 1_000_000, 10_000_000]
+    assert sw["nnz"][1] is sw["dims"][1]
+    assert abs(sw["time_ratio_I_1e6_over_1e3"] - (1.0 + 1.0 + 1.0) / (1.0 + 0.001 + 1.0)) < 1e-12
+    assert abs(sw["time_ratio_nnz_1e7_over_1e6"] - (1.0 + 0.01 + 10.0) / (1.0 + 0.01 + 1.0)) < 1e-12
+    assert sw["entries_ratio_nnz_1e7_over_1e6"] == 10.0
+
+
+def test_cp_entry_bytes():
+    # 3-way rank 10 FP32: 12 B of indices + 4 B value + 3 rows of 40 B read and written
+    assert bench.cp_entry_bytes(3, 10, "f32") == (16 + 240, 12 + 160)
+    # FP64 doubles the value and row bytes, not the 4-byte indices
+    assert bench.cp_entry_bytes(4, 8, "f64") == (16 + 8 + 2 * 8 * 8 * 4, 8 + 8 + 4 * 8 * 8)
